@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs shared by the oracle tests and the HIP path.
+
+This module holds only input generation: macro meshes (vertex lists), nodal
+coefficient fields and random vectors.  It contains none of the stencil-scaling
+arithmetic, so both the CPU oracle and the GPU library can consume its outputs
+without sharing any of the method's code.
+
+Workloads (the paper's setting of vector-valued P1 elasticity / generalized
+Newtonian operators on uniformly refined macro-tetrahedra, Sec. 2 and Sec. 5):
+
+* ``unit_tet``   one reference macro-tet, level 4 (969 nodes), k = 1 + 0.5
+                 sin(2 pi x) sin(2 pi y) sin(2 pi z), Lame mu = 1, lambda = k.
+* ``kuhn6``      unit cube cut into 6 macro-tets along the main diagonal
+                 (vertex order 0, e_s1, e_s1+e_s2, 1 for every permutation s),
+                 level 7, k = exp(g) with g a 16-mode smooth random field of
+                 amplitude 1; paper's E-form elasticity with nu = 0.34 (Sec. 5.1.2).
+* ``cube24``     unit cube: every face cut into 4 triangles through its centre,
+                 every triangle joined to the cube centre (24 congruent macros),
+                 level 7, Carreau viscosity of a seeded smooth velocity field.
+* ``batch256``   256 independent unit macro-tets, levels uniform in 3..6, each
+                 with its own Fourier coefficient field.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+SEED_BASE = 190808666
+
+
+def rng_for(config_id: int, salt: int = 0) -> np.random.Generator:
+    """Seeded generator for a workload id (config 1..5) and a salt."""
+    return np.random.default_rng([SEED_BASE + config_id, salt])
+
+
+# ---------------------------------------------------------------- macro meshes
+
+def unit_tet() -> np.ndarray:
+    """Reference macro-tet (0,0,0),(1,0,0),(0,1,0),(0,0,1); shape (1,4,3)."""
+    return np.array([[[0.0, 0.0, 0.0], [1.0, 0.0, 0.0],
+                      [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]])
+
+
+def kuhn6() -> np.ndarray:
+    """Unit cube split into 6 tets sharing the main diagonal; shape (6,4,3).
+
+    Vertex order (0, e_s1, e_s1 + e_s2, (1,1,1)) for each permutation s, so
+    every macro's micro-lattice is the same Freudenthal lattice of the cube.
+    """
+    eye = np.eye(3)
+    out = []
+    for s in itertools.permutations(range(3)):
+        v1 = eye[s[0]]
+        v2 = v1 + eye[s[1]]
+        out.append([np.zeros(3), v1, v2, np.ones(3)])
+    return np.array(out, dtype=np.float64)
+
+
+def cube24() -> np.ndarray:
+    """Unit cube: each face split into 4 triangles through the face centre,
+    each triangle joined to the cube centre; shape (24,4,3).
+
+    Vertex order (cube centre, face centre, corner a, corner b) with corners
+    a, b consecutive around the face.
+    """
+    c = np.full(3, 0.5)
+    out = []
+    for axis in range(3):
+        for side in (0.0, 1.0):
+            fc = np.full(3, 0.5)
+            fc[axis] = side
+            u, w = [a for a in range(3) if a != axis]
+            ring = []
+            for du, dw in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                p = np.zeros(3)
+                p[axis] = side
+                p[u] = du
+                p[w] = dw
+                ring.append(p)
+            for q in range(4):
+                out.append([c, fc, ring[q], ring[(q + 1) % 4]])
+    return np.array(out, dtype=np.float64)
+
+
+def batch_levels(n_problems: int = 256, lo: int = 3, hi: int = 6,
+                 config_id: int = 4) -> np.ndarray:
+    """Levels of the independent batched problems, uniform in lo..hi."""
+    return rng_for(config_id, 1).integers(lo, hi + 1, size=n_problems).astype(np.int32)
+
+
+def batch_field_params(n_problems: int = 256, config_id: int = 4):
+    """Per-problem (n_modes, amplitude) for the batched workload."""
+    r = rng_for(config_id, 2)
+    modes = r.integers(4, 33, size=n_problems)
+    amps = r.uniform(0.5, 2.0, size=n_problems)
+    return modes, amps
+
+
+# -------------------------------------------------------------- nodal fields
+
+def sine_coefficient(xyz: np.ndarray) -> np.ndarray:
+    """k(x) = 1 + 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z) at points (N,3)."""
+    s = np.sin(2.0 * np.pi * xyz)
+    return 1.0 + 0.5 * s[:, 0] * s[:, 1] * s[:, 2]
+
+
+def affine_coefficient(xyz: np.ndarray, a0=1.5, grad=(0.3, -0.2, 0.45)) -> np.ndarray:
+    """A globally affine positive coefficient a0 + grad . x."""
+    return a0 + xyz @ np.asarray(grad, dtype=np.float64)
+
+
+def fourier_modes(rng: np.random.Generator, n_modes: int, kmax: int = 4):
+    """Draw n_modes wave vectors in {-kmax..kmax}^3 \\ {0}, phases, amplitudes."""
+    kv = []
+    while len(kv) < n_modes:
+        v = rng.integers(-kmax, kmax + 1, size=3)
+        if np.any(v != 0):
+            kv.append(v)
+    kv = np.array(kv, dtype=np.float64)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    amp = rng.uniform(-1.0, 1.0, size=n_modes)
+    return kv, phase, amp
+
+
+def fourier_field(xyz: np.ndarray, rng: np.random.Generator, n_modes: int,
+                  amplitude: float) -> np.ndarray:
+    """Smooth random field g = sum_m a_m cos(2 pi kappa_m . x + phi_m), rescaled
+    so that max |g| over the given points equals ``amplitude``."""
+    kv, phase, amp = fourier_modes(rng, n_modes)
+    g = np.cos(2.0 * np.pi * xyz @ kv.T + phase) @ amp
+    m = np.max(np.abs(g))
+    return g * (amplitude / m) if m > 0 else g
+
+
+def exp_fourier_coefficient(xyz: np.ndarray, rng: np.random.Generator,
+                            n_modes: int = 16, amplitude: float = 1.0) -> np.ndarray:
+    """k = exp(g) with g a Fourier field of the given amplitude (k in [e^-A, e^A])."""
+    return np.exp(fourier_field(xyz, rng, n_modes, amplitude))
+
+
+def velocity_modes(rng: np.random.Generator, n_modes: int = 8, kmax: int = 3):
+    kv = []
+    while len(kv) < n_modes:
+        v = rng.integers(-kmax, kmax + 1, size=3)
+        if np.any(v != 0):
+            kv.append(v)
+    kv = np.array(kv, dtype=np.float64)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    b = rng.uniform(-1.0, 1.0, size=(n_modes, 3))
+    return kv, phase, b
+
+
+def velocity_field(xyz: np.ndarray, rng: np.random.Generator, scale: float,
+                   n_modes: int = 8) -> np.ndarray:
+    """Smooth velocity u(x) = A sum_m b_m sin(2 pi kappa_m . x + phi_m); (N,3)."""
+    kv, phase, b = velocity_modes(rng, n_modes)
+    return scale * (np.sin(2.0 * np.pi * xyz @ kv.T + phase) @ b)
+
+
+def velocity_gradient(xyz: np.ndarray, rng: np.random.Generator, scale: float,
+                      n_modes: int = 8) -> np.ndarray:
+    """Analytic gradient G[n, c, d] = d u_c / d x_d of ``velocity_field`` drawn
+    from an identically seeded generator."""
+    kv, phase, b = velocity_modes(rng, n_modes)
+    cosv = np.cos(2.0 * np.pi * xyz @ kv.T + phase)          # (N, M)
+    return scale * 2.0 * np.pi * np.einsum('nm,mc,md->ncd', cosv, b, kv)
+
+
+def uniform_vector(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Entries U(-1, 1), float64."""
+    return rng.uniform(-1.0, 1.0, size=n)
+
+
+# ------------------------------------------------------- material constants
+
+def eform_weights(nu: float = 0.34):
+    """Paper's single-coefficient elasticity form (Sec. 5.1.2): E scales
+    (1/(1+nu)) (eps, eps) + nu/((1+nu)(1-2nu)) (div, div).
+
+    Returned as (mu, lam) with the form written 2 mu (eps, eps) + lam (div, div).
+    """
+    return 1.0 / (2.0 * (1.0 + nu)), nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+
+
+CARREAU_DEFAULT = dict(eta0=1.0, eta_inf=1e-3, kappa=1.0, r=-0.25)
