@@ -1,0 +1,208 @@
+"""Benchmark of the physical stencil-scaling apply on one MI355X.
+
+Workload (one "step" = one application y = A_s(k) x of the whole operator:
+macro-interior rows, macro-boundary rows and the copy-group sum): the unit
+cube cut into 6 macro-tets along its main diagonal, every macro refined to
+level 7 (129 points per macro edge, 2,146,689 distinct nodes, 6,145,149
+unknowns after homogeneous Dirichlet conditions on the cube boundary),
+E-form elasticity with nu = 0.34 scaled by k = exp(g), g a seeded 16-mode
+Fourier field of amplitude 1, x ~ U(-1, 1).  Synthetic data; FP64.
+
+Inputs rotate over 5 buffer sets (5 x 123 MB) so that consecutive steps do
+not hit the 256 MB Infinity Cache.  The timed region is bracketed by
+torch.cuda.synchronize() and HIP events on the launch stream; the library's
+own per-kernel events give the interior kernel's average duration for the
+roofline line.
+
+Prints ONE JSON line.  Options: --gpus (must be 1), --steps, --warmup,
+--level, --no-cpu-baseline, --extra (also time FP32, on-the-fly and the
+residual).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_INTERIOR_NODE = {"f64": 56.0, "f32": 28.0}   # x (3) + k (1) read, y (3) written
+N_SETS = 5
+
+
+def consistent_random(mesh, rng, shape_first):
+    """U(-1,1) values per distinct node, copied to every copy slot."""
+    import numpy as np
+    fl = mesh.flags()
+    xyz = mesh.coords().T
+    owners = np.nonzero(fl & 2)[0]
+    from scipy.spatial import cKDTree
+    _, idx = cKDTree(xyz[owners]).query(xyz)
+    vals = rng.uniform(-1.0, 1.0, size=(shape_first, owners.shape[0]))
+    return np.ascontiguousarray(vals[:, idx])
+
+
+def cpu_baseline(level, rows_sample, seed=0):
+    """Time the CPU oracle on a sample of rows of the same workload."""
+    import numpy as np
+    import workloads as W
+    from oracle import operators as O
+    from oracle.mesh import MacroMesh
+    mu, lam = W.eform_weights()
+    orc = MacroMesh(W.kuhn6(), level)
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(2, 0), 16, 1.0)
+    x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(2, 1)).reshape(-1, 3)
+    rows = np.random.default_rng(seed).choice(orc.unknown, min(rows_sample, orc.unknown.shape[0]),
+                                              replace=False)
+    t0 = time.perf_counter()
+    O.apply(orc, k, dict(mu1=mu, lam1=lam), x, rows=rows)
+    dt = time.perf_counter() - t0
+    return dict(value=3 * rows.shape[0] / dt / 1e6, unit="MDoF/s", cores=1, kind="oracle",
+                seconds=round(dt, 2),
+                sample=f"{rows.shape[0]} sampled unknown rows of the same level-{level} workload "
+                       f"(oracle assembles each row by the Lemma from its elements, then multiplies); "
+                       f"single-threaded NumPy")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--level", type=int, default=7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=40000)
+    ap.add_argument("--extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
+              f"is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1908_08666_amd import Mesh
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    mu, lam = W.eform_weights()
+    mesh = Mesh(W.kuhn6(), args.level, mu1=mu, lam1=lam)
+    n = 1 << args.level
+    N = mesh.n_nodes
+    dofs = 3 * mesh.n_unknown
+    interior_rows = mesh.n_macro * (n - 1) * (n - 2) * (n - 3) // 6
+    xyz = mesh.coords().T
+    k_np = W.exp_fourier_coefficient(xyz, W.rng_for(2, 0), 16, 1.0)
+
+    def make_sets(dtype):
+        sets = []
+        for s in range(N_SETS):
+            x = torch.from_numpy(consistent_random(mesh, W.rng_for(2, 10 + s), 3)).to(dev, dtype)
+            k = torch.from_numpy(k_np).to(dev, dtype)
+            y = torch.empty_like(x)
+            sets.append((x, k, y))
+        return sets
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, sets, steps, warmup, profile=True):
+        for w in range(warmup):
+            fn(*sets[w % N_SETS])
+        torch.cuda.synchronize()
+        if profile:
+            mesh.profile_enable(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for s in range(steps):
+            fn(*sets[s % N_SETS])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms = e0.elapsed_time(e1)
+        prof = mesh.profile_read() if profile else {}
+        if profile:
+            mesh.profile_enable(False)
+        return total_ms, prof
+
+    sets64 = make_sets(torch.float64)
+    total_ms, prof = timed(lambda x, k, y: mesh.apply_scaled(x, k, y), sets64, args.steps,
+                           args.warmup)
+    ms_per_step = total_ms / args.steps
+    value = dofs / (ms_per_step * 1e-3) / 1e6
+
+    nl, int_ms = prof["interior_scaled"]
+    avg_int_ms = int_ms / max(nl, 1)
+    alg_bytes = BYTES_PER_INTERIOR_NODE["f64"] * interior_rows
+    achieved = alg_bytes / (avg_int_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="k_interior<double, scaled>",
+                    avg_kernel_ms=round(avg_int_ms, 5),
+                    bytes_per_launch=int(alg_bytes),
+                    units_per_launch=interior_rows, bytes_per_unit=56)
+    kernels = {name: dict(launches=c, avg_ms=round(ms / c, 5) if c else None)
+               for name, (c, ms) in prof.items()}
+
+    extra = {}
+    if args.extra:
+        del sets64
+        torch.cuda.empty_cache()
+        sets64 = make_sets(torch.float64)
+        t_fly, p_fly = timed(lambda x, k, y: mesh.apply_onthefly(x, k, y), sets64,
+                             max(args.steps // 4, 5), 5)
+        extra["onthefly_f64_MDoF_s"] = round(dofs / (t_fly / max(args.steps // 4, 5) * 1e-3) / 1e6, 1)
+        c, ms = p_fly["interior_onthefly"]
+        extra["onthefly_f64_interior_avg_ms"] = round(ms / max(c, 1), 5)
+        t_res, _ = timed(lambda x, k, y: mesh.residual(x, x, k, y), sets64, max(args.steps // 4, 5),
+                         5, profile=False)
+        extra["residual_f64_MDoF_s"] = round(dofs / (t_res / max(args.steps // 4, 5) * 1e-3) / 1e6, 1)
+        del sets64
+        torch.cuda.empty_cache()
+        sets32 = make_sets(torch.float32)
+        t32, p32 = timed(lambda x, k, y: mesh.apply_scaled(x, k, y), sets32, args.steps, args.warmup)
+        extra["scaled_f32_MDoF_s"] = round(dofs / (t32 / args.steps * 1e-3) / 1e6, 1)
+        c, ms = p32["interior_scaled"]
+        a32 = BYTES_PER_INTERIOR_NODE["f32"] * interior_rows / (ms / max(c, 1) * 1e-3) / 1e9
+        extra["scaled_f32_interior_avg_ms"] = round(ms / max(c, 1), 5)
+        extra["scaled_f32_interior_GBs"] = round(a32, 1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.level, args.cpu_rows)
+
+    out = {
+        "metric": "scaled-stencil apply MDoF/s + %HBM peak; CG time to 1e-8 (FP64 vs FP32+IR vs learned)",
+        "value": round(value, 1),
+        "unit": "MDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"elasticity E-form (nu=0.34), unit cube as 6 macro-tets at level "
+                               f"{args.level}, k=exp(16-mode Fourier field, amplitude 1), "
+                               f"physical stencil scaling apply",
+                   "level": args.level, "macros": mesh.n_macro, "distinct_nodes_unknown": mesh.n_unknown,
+                   "dofs_per_step": dofs, "slots": N, "interior_rows": interior_rows,
+                   "buffer_sets": N_SETS},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    if extra:
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

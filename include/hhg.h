@@ -1,0 +1,183 @@
+/*
+ * hhg.h -- C ABI of the MI355X (gfx950) library for matrix-free stencil
+ * scaling on hierarchical hybrid grids.
+ *
+ * Method: Drzisga, Ruede, Wohlmuth, "Stencil scaling for vector-valued PDEs on
+ * hybrid grids with applications to generalized Newtonian fluids".  A macro
+ * tetrahedral mesh is refined uniformly; inside every macro-tet the operator
+ * of the vector-valued P1 form
+ *
+ *     a(u, v) = (2 mu(x) eps(u), eps(v)) + (lam(x) div u, div v)          (Sec. 2,
+ *                                                   eq. bilinearformstd)
+ *
+ * with mu = mu0 + mu1 k, lam = lam0 + lam1 k for ONE nodal scalar field k is
+ * applied by scaling constant reference stencils with nodal coefficient
+ * averages plus the antisymmetric correction of the Lemma (eqs.
+ * bilinearformscaling, patchmean, corrtermgeneral; 3-D form of Sec. 2.4),
+ * instead of integrating the form element by element.
+ *
+ * Data layout (all vectors live in device memory, owned by the caller):
+ *   * Nodes are stored per macro: macro m occupies slots
+ *     [macro_offset[m], macro_offset[m+1]).  Inside a macro of level L
+ *     (n = 2^L intervals per edge) node (i, j, k), i,j,k >= 0, i+j+k <= n, at
+ *         x0 + (i/n)(x1-x0) + (j/n)(x2-x0) + (k/n)(x3-x0)
+ *     sits at local slot  P(k) + (i+j)(i+j+1)/2 + i,  P(k) = nodes in planes
+ *     below k.  Nodes on faces, edges and vertices shared by several macros
+ *     appear once per macro ("copies"); a vector is CONSISTENT when all copies
+ *     of a node hold the same value.  Every output of this library is
+ *     consistent; inputs must be consistent.
+ *   * A vector field is SoA [3][n_nodes] (component c of slot s at
+ *     c*n_nodes + s); the coefficient k is [n_nodes].  Element type double
+ *     (HHG_F64) or float (HHG_F32) as selected by `prec`.  Pointers must be
+ *     16-byte aligned.
+ *   * Homogeneous Dirichlet nodes (outer boundary of the macro mesh, Sec. 2):
+ *     their entries of x are ignored (treated as 0) and their entries of every
+ *     operator output are written as 0.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * Apply/residual calls are asynchronous on that stream; solver calls
+ * synchronize it before returning.
+ *
+ * Errors: every call returns HHG_OK (0) or a negative code; the text of the
+ * last error of the calling thread is returned by hhg_last_error().  No C++
+ * exception crosses this interface.  A handle must not be used by two host
+ * threads at once.
+ */
+#ifndef HHG_H
+#define HHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hhg_ctx *hhg_handle;
+
+enum hhg_status {
+  HHG_OK = 0,
+  HHG_EINVAL = -1,      /* bad argument: null/misaligned pointer, level out of
+                           range, degenerate macro, unknown enum value        */
+  HHG_EHIP = -2,        /* HIP runtime error (text in hhg_last_error)         */
+  HHG_ENOCONV = -3,     /* solver reached maxit; x and info are still written */
+  HHG_EBREAKDOWN = -4,  /* solver breakdown: NaN/Inf or p^T A p <= 0          */
+  HHG_ENOMEM = -5       /* device or host allocation failed                   */
+};
+
+enum hhg_prec { HHG_F64 = 0, HHG_F32 = 1 };
+enum hhg_coupling { HHG_CONFORMING = 0, HHG_INDEPENDENT = 1 };
+enum hhg_dirichlet { HHG_DIRICHLET_OUTER = 0, HHG_DIRICHLET_NONE = 1 };
+enum hhg_corr { HHG_CORR_PHYSICAL = 0, HHG_CORR_NONE = 1 };
+enum hhg_khat { HHG_KHAT_PATCH = 0, HHG_KHAT_EDGE = 1 };
+enum hhg_iface { HHG_IFACE_SYMMETRIC = 0, HHG_IFACE_ROWWISE = 1 };
+enum hhg_method { HHG_METHOD_SCALED = 0, HHG_METHOD_ONTHEFLY = 1 };
+
+/* Macro mesh (Sec. 2: macro triangulation T_H refined uniformly).
+ *   verts     host, [n_macro][4][3] vertex coordinates; the vertex order fixes
+ *             each macro's index space (see the layout above).
+ *   level     host, [n_macro]; 2 <= level <= 9 (a macro needs an interior
+ *             vertex, Sec. 2).  CONFORMING meshes need one common level.
+ *   coupling  HHG_CONFORMING: macros sharing faces/edges/vertices (matched by
+ *             coordinates) form one problem; HHG_INDEPENDENT: every macro is
+ *             its own problem (batched use).
+ *   dirichlet HHG_DIRICHLET_OUTER: homogeneous Dirichlet on every macro face
+ *             owned by a single macro (and on its edges and vertices);
+ *             HHG_DIRICHLET_NONE: pure Neumann operator.                     */
+typedef struct {
+  int32_t n_macro;
+  const double *verts;
+  const int32_t *level;
+  int32_t coupling;
+  int32_t dirichlet;
+} hhg_mesh_desc;
+
+/* Operator: 2 (mu0 + mu1 k) (eps, eps) + (lam0 + lam1 k) (div, div).
+ *   corr   HHG_CORR_PHYSICAL: physical scaling (Lemma); HHG_CORR_NONE:
+ *          unphysical scaling, R omitted (eq. stencilscalingwithoutcorr).
+ *   khat   HHG_KHAT_PATCH: patch mean of the element means (eq. patchmean);
+ *          HHG_KHAT_EDGE: (k_i + k_j)/2 (Remark after the Lemma).
+ *   iface  rows of nodes on a macro boundary (Sec. 2.2):
+ *          HHG_IFACE_SYMMETRIC: nodal-integration entries where both nodes lie
+ *          on the macro boundary (and on the diagonal), scaled entries
+ *          towards macro-interior nodes -- a symmetric matrix;
+ *          HHG_IFACE_ROWWISE: the full nodal-integration row.                 */
+typedef struct {
+  double mu0, lam0;
+  double mu1, lam1;
+  int32_t corr;
+  int32_t khat;
+  int32_t iface;
+} hhg_op_desc;
+
+/* Host-side setup (Sec. 2.4: reference stencil and correction stencils are
+ * precomputed once per macro).  Builds the per-macro constant tables in FP64
+ * (and their FP32 copies), the interface-copy groups and the Dirichlet masks.
+ * No device memory is touched here: the tables (a few KB per macro) are
+ * uploaded to the current HIP device by the first device call, and the handle
+ * may then only be used on that device.  On success *out owns host and device
+ * memory until hhg_destroy.  Errors: HHG_EINVAL for null pointers,
+ * n_macro < 1, a level outside 2..9, mixed levels in a conforming mesh, a
+ * degenerate macro (|det| < 1e-12 |edges|^3) or unknown enum values;
+ * HHG_EHIP / HHG_ENOMEM on device failures.                                  */
+int hhg_setup_macro(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_handle *out);
+
+/* Frees the handle's device and host memory.  NULL is accepted.            */
+int hhg_destroy(hhg_handle h);
+
+/* Sizes: *n_nodes total slots (copies included), *n_unknown number of
+ * distinct non-Dirichlet nodes (3 unknowns each); macro_offset, if not NULL,
+ * receives n_macro+1 slot offsets (host memory).                            */
+int hhg_layout(hhg_handle h, int64_t *n_nodes, int64_t *n_unknown, int64_t *macro_offset);
+
+/* Host output [3][n_nodes] of slot coordinates (caller-allocated).         */
+int hhg_node_coords(hhg_handle h, double *xyz);
+
+/* Host output [n_nodes] bit flags per slot: bit0 Dirichlet, bit1 owner copy
+ * (exactly one copy of every distinct node), bit2 on a macro boundary, bit3
+ * non-Dirichlet node with copies in other macros.                          */
+int hhg_node_flags(hhg_handle h, uint8_t *flags);
+
+/* y = A_s(k) x: physical (or unphysical) stencil scaling in macro interiors
+ * (Lemma, Sec. 2.4) and the chosen interface rule on macro boundaries
+ * (Sec. 2.2).  x [3][n], k [n], y [3][n] device pointers of type `prec`; x
+ * and y must not overlap.  Asynchronous on `stream`.                        */
+int hhg_apply_scaled(hhg_handle h, int32_t prec, const void *x, const void *k, void *y,
+                     void *stream);
+
+/* y = A_n(k) x: nodal integration computed element by element on the fly
+ * (eq. nodalintegration with the vertex mean of eq. nodalquad) -- the
+ * comparison method of Sec. 4 and Sec. 5.  Same arguments as above.        */
+int hhg_apply_onthefly(hhg_handle h, int32_t prec, const void *x, const void *k, void *y,
+                       void *stream);
+
+/* r = f - A x with A = A_s (method HHG_METHOD_SCALED) or A_n
+ * (HHG_METHOD_ONTHEFLY); the residual of Sec. 4 (eq. residuallinalg).
+ * Dirichlet entries of r are 0.  r must not overlap x or f.                 */
+int hhg_residual(hhg_handle h, int32_t prec, int32_t method, const void *f, const void *x,
+                 const void *k, void *r, void *stream);
+
+/* Kernel timing (tracing aid, not needed for results).  While enabled,
+ * every kernel the library launches is bracketed by a pair of HIP events on
+ * the launch stream.  hhg_profile_read synchronizes those events and returns,
+ * per kernel id, the number of launches and the summed duration in ms since
+ * enabling; ids: 0 interior scaled apply, 1 interior on-the-fly apply,
+ * 2 macro-boundary rows, 3 copy-group sum.  Enabling resets the counters.    */
+enum hhg_kernel_id {
+  HHG_K_INTERIOR_SCALED = 0,
+  HHG_K_INTERIOR_ONTHEFLY = 1,
+  HHG_K_BOUNDARY_ROWS = 2,
+  HHG_K_GROUP_SUM = 3,
+  HHG_K_COUNT = 16
+};
+int hhg_profile_enable(hhg_handle h, int32_t on);
+int hhg_profile_read(hhg_handle h, int32_t kernel_id, int64_t *launches, double *total_ms);
+
+/* Text of the calling thread's last error ("" if none).                    */
+const char *hhg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HHG_H */

@@ -66,7 +66,9 @@ def reference_refinement(level: int):
     for _ in range(level):
         t = bey_children(t)
     flat = t.reshape(-1, 3)
-    ijk, inv = np.unique(flat, axis=0, return_inverse=True)
+    key = flat[:, 0] * (n + 1) ** 2 + flat[:, 1] * (n + 1) + flat[:, 2]
+    ukey, inv = np.unique(key, return_inverse=True)
+    ijk = np.column_stack([ukey // (n + 1) ** 2, (ukey // (n + 1)) % (n + 1), ukey % (n + 1)])
     tets = inv.reshape(-1, 4).astype(np.int64)
     ijk.setflags(write=False)
     tets.setflags(write=False)

@@ -121,20 +121,28 @@ def _to_csr(mesh, R, C, V):
     return A
 
 
-def _tet_lookup(tets: np.ndarray):
-    """Sorted structured keys of element vertex sets for membership queries."""
-    key = np.sort(tets, axis=1).astype(np.int64)
-    dt = np.dtype([("a", np.int64), ("b", np.int64), ("c", np.int64), ("d", np.int64)])
-    skey = np.ascontiguousarray(key).view(dt).ravel()
-    order = np.argsort(skey, kind="stable")
-    return skey[order], order, dt
+def _set_keys(verts: np.ndarray, N: int) -> np.ndarray:
+    """Exact key of a 4-vertex set: sorted ids (a<b<c<d) packed as the complex
+    number (a N + b) + i (c N + d); exact in float64 while N^2 < 2^53, and
+    complex arrays sort lexicographically (real part, then imaginary)."""
+    v = np.sort(verts, axis=1).astype(np.float64)
+    return (v[:, 0] * N + v[:, 1]) + 1j * (v[:, 2] * N + v[:, 3])
+
+
+def _tet_lookup(tets: np.ndarray, N: int):
+    """Sorted element keys for membership queries of vertex sets."""
+    if float(N) * N >= 2.0 ** 53:
+        raise ValueError("macro too large for exact element keys")
+    key = _set_keys(tets, N)
+    order = np.argsort(key, kind="stable")
+    return key[order], order, N
 
 
 def _find_tets(lookup, query: np.ndarray) -> np.ndarray:
-    skey, order, dt = lookup
-    q = np.ascontiguousarray(np.sort(query, axis=1).astype(np.int64)).view(dt).ravel()
-    pos = np.searchsorted(skey, q)
-    pos = np.minimum(pos, skey.shape[0] - 1)
+    """Element id of each queried vertex set, -1 if it is not an element."""
+    skey, order, N = lookup
+    q = _set_keys(query, N)
+    pos = np.minimum(np.searchsorted(skey, q), skey.shape[0] - 1)
     hit = skey[pos] == q
     return np.where(hit, order[pos], -1)
 
@@ -179,7 +187,7 @@ def scaled_matrix(mesh: MacroMesh, k, op, rows=None, corr="physical",
         # dense lookup of index triples -> local node id (for reflections)
         cube = np.full((n + 1,) * 3, -1, dtype=np.int64)
         cube[ijk[:, 0], ijk[:, 1], ijk[:, 2]] = np.arange(N)
-        lookup = _tet_lookup(all_tets)
+        lookup = _tet_lookup(all_tets, N)
 
         # all (element, test vertex a, trial vertex b), a != b
         T = tets.shape[0]

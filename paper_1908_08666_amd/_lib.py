@@ -1,0 +1,84 @@
+"""ctypes declarations of the C ABI in include/hhg.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhhg.so")
+
+HHG_OK, HHG_EINVAL, HHG_EHIP, HHG_ENOCONV, HHG_EBREAKDOWN, HHG_ENOMEM = 0, -1, -2, -3, -4, -5
+HHG_F64, HHG_F32 = 0, 1
+HHG_CONFORMING, HHG_INDEPENDENT = 0, 1
+HHG_DIRICHLET_OUTER, HHG_DIRICHLET_NONE = 0, 1
+HHG_CORR_PHYSICAL, HHG_CORR_NONE = 0, 1
+HHG_KHAT_PATCH, HHG_KHAT_EDGE = 0, 1
+HHG_IFACE_SYMMETRIC, HHG_IFACE_ROWWISE = 0, 1
+HHG_METHOD_SCALED, HHG_METHOD_ONTHEFLY = 0, 1
+HHG_K_INTERIOR_SCALED, HHG_K_INTERIOR_ONTHEFLY, HHG_K_BOUNDARY_ROWS, HHG_K_GROUP_SUM = 0, 1, 2, 3
+KERNEL_NAMES = {0: "interior_scaled", 1: "interior_onthefly", 2: "boundary_rows", 3: "group_sum"}
+
+STATUS_NAMES = {0: "HHG_OK", -1: "HHG_EINVAL", -2: "HHG_EHIP", -3: "HHG_ENOCONV",
+                -4: "HHG_EBREAKDOWN", -5: "HHG_ENOMEM"}
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int32), ("verts", ctypes.POINTER(ctypes.c_double)),
+                ("level", ctypes.POINTER(ctypes.c_int32)), ("coupling", ctypes.c_int32),
+                ("dirichlet", ctypes.c_int32)]
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("mu0", ctypes.c_double), ("lam0", ctypes.c_double), ("mu1", ctypes.c_double),
+                ("lam1", ctypes.c_double), ("corr", ctypes.c_int32), ("khat", ctypes.c_int32),
+                ("iface", ctypes.c_int32)]
+
+
+class HHGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+SIGNATURES = {
+    "hhg_setup_macro": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(OpDesc), ctypes.POINTER(_VP)], ctypes.c_int),
+    "hhg_destroy": ([_VP], ctypes.c_int),
+    "hhg_layout": ([_VP, _I64P, _I64P, _I64P], ctypes.c_int),
+    "hhg_node_coords": ([_VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hhg_node_flags": ([_VP, ctypes.POINTER(ctypes.c_uint8)], ctypes.c_int),
+    "hhg_apply_scaled": ([_VP, _I32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_apply_onthefly": ([_VP, _I32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_residual": ([_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
+    "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hhg_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """Load libhhg.so from the package directory; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != HHG_OK:
+        msg = lib().hhg_last_error()
+        raise HHGError(code, msg.decode() if msg else "")
+    return code

@@ -1,0 +1,82 @@
+// Handle definition and host helpers shared by the library's translation units.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hhg_internal.h"
+
+struct hhg_ctx {
+  int n_macro = 0;
+  int coupling = HHG_CONFORMING;
+  int dirichlet = HHG_DIRICHLET_OUTER;
+  hhg_op_desc op{};
+  int max_level = 0;
+  int64_t n_nodes = 0;
+  int64_t n_unknown = 0;
+  std::vector<double> verts;                 // [n_macro][4][3]
+  std::vector<hhg::MacroInfo> minfo;         // host copy
+  std::vector<uint8_t> flags;                // per slot: bit0 Dirichlet, bit1 owner, bit2 boundary,
+                                             // bit3 node has copies in other macros
+  std::vector<hhg::StencilConst<double>> sc64;
+  std::vector<hhg::ElemConst<double>> ec64;
+  std::vector<hhg::WorkItem> work;
+  std::vector<int2> bslot;
+  std::vector<int64_t> grp_ptr, grp_slot;
+  int planes_per_item = 16;
+  bool on_device = false;                    // tables uploaded (first device call)
+  int device = -1;
+
+  // device copies
+  hhg::MacroInfo *d_minfo = nullptr;
+  hhg::StencilConst<double> *d_sc64 = nullptr;
+  hhg::StencilConst<float> *d_sc32 = nullptr;
+  hhg::ElemConst<double> *d_ec64 = nullptr;
+  hhg::ElemConst<float> *d_ec32 = nullptr;
+  hhg::WorkItem *d_work = nullptr;
+  int n_work = 0;
+  int2 *d_bslot = nullptr;                   // (macro, packed i | j<<10 | k<<20)
+  int64_t n_bslot = 0;
+  int64_t *d_grp_ptr = nullptr;              // interface copy groups (>= 2 copies)
+  int64_t *d_grp_slot = nullptr;
+  int64_t n_grp = 0;
+  uint8_t *d_flags = nullptr;
+
+  // kernel timing (hhg_profile_*)
+  struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[HHG_K_COUNT] = {};
+  int64_t prof_n[HHG_K_COUNT] = {};
+};
+
+namespace hhg {
+int ensure_device(hhg_ctx *h);
+
+// Brackets one kernel launch with events when profiling is enabled.
+class ProfScope {
+ public:
+  ProfScope(hhg_ctx *h, int kid, hipStream_t st);
+  ~ProfScope();
+
+ private:
+  hhg_ctx *h_;
+  int kid_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr;
+};
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+}  // namespace hhg
+
+#define HHG_HIP(call)                                      \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hhg::hip_fail(e_, #call); \
+  } while (0)

@@ -1,0 +1,154 @@
+"""Python binding of the C ABI: a macro mesh handle plus operator calls.
+
+Only argument marshalling happens here; every step of an operator
+application runs in the HIP kernels of libhhg.so.  Device vectors are torch
+tensors on a ROCm device (SoA [3, n_nodes] for vector fields, [n_nodes] for the
+coefficient), float64 or float32.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _prec_of(t):
+    import torch
+    if t.dtype == torch.float64:
+        return L.HHG_F64
+    if t.dtype == torch.float32:
+        return L.HHG_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev_ptr(t, shape, dtype):
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"shape {tuple(t.shape)} != {tuple(shape)}")
+    if t.dtype != dtype:
+        raise TypeError(f"dtype {t.dtype} != {dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Handle of a macro mesh with its operator (``hhg_setup_macro``).
+
+    Parameters mirror ``hhg_mesh_desc`` / ``hhg_op_desc``: ``verts`` (M,4,3),
+    ``levels`` int or (M,), weights of 2 (mu0 + mu1 k)(eps, eps) +
+    (lam0 + lam1 k)(div, div), and the variant flags.
+    """
+
+    def __init__(self, verts, levels, mu0=0.0, lam0=0.0, mu1=0.0, lam1=0.0,
+                 coupling="conforming", dirichlet="outer", corr="physical",
+                 khat="patch", iface="symmetric"):
+        verts = np.ascontiguousarray(verts, dtype=np.float64)
+        M = verts.shape[0]
+        lv = np.ascontiguousarray(np.broadcast_to(np.asarray(levels, dtype=np.int32), (M,)))
+        md = L.MeshDesc(M, verts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        {"conforming": L.HHG_CONFORMING, "independent": L.HHG_INDEPENDENT}[coupling],
+                        {"outer": L.HHG_DIRICHLET_OUTER, "none": L.HHG_DIRICHLET_NONE}[dirichlet])
+        od = L.OpDesc(mu0, lam0, mu1, lam1,
+                      {"physical": L.HHG_CORR_PHYSICAL, "none": L.HHG_CORR_NONE}[corr],
+                      {"patch": L.HHG_KHAT_PATCH, "edge": L.HHG_KHAT_EDGE}[khat],
+                      {"symmetric": L.HHG_IFACE_SYMMETRIC, "rowwise": L.HHG_IFACE_ROWWISE}[iface])
+        h = ctypes.c_void_p()
+        self._lib = L.lib()
+        L.check(self._lib.hhg_setup_macro(ctypes.byref(md), ctypes.byref(od), ctypes.byref(h)))
+        self._h = h
+        self.n_macro = M
+        self.levels = lv.copy()
+        nn = ctypes.c_int64()
+        nu = ctypes.c_int64()
+        off = np.zeros(M + 1, dtype=np.int64)
+        L.check(self._lib.hhg_layout(h, ctypes.byref(nn), ctypes.byref(nu),
+                                     off.ctypes.data_as(L._I64P)))
+        self.n_nodes = int(nn.value)
+        self.n_unknown = int(nu.value)
+        self.macro_offset = off
+
+    # --------------------------------------------------------------- host
+    def coords(self) -> np.ndarray:
+        out = np.zeros((3, self.n_nodes), dtype=np.float64)
+        L.check(self._lib.hhg_node_coords(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def flags(self) -> np.ndarray:
+        out = np.zeros(self.n_nodes, dtype=np.uint8)
+        L.check(self._lib.hhg_node_flags(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out
+
+    # ------------------------------------------------------------- device
+    def _vec_args(self, x, k, y):
+        prec = _prec_of(x)
+        dt = x.dtype
+        N = self.n_nodes
+        return (prec, _dev_ptr(x, (3, N), dt), _dev_ptr(k, (N,), dt), _dev_ptr(y, (3, N), dt))
+
+    def apply_scaled(self, x, k, y=None, stream=None):
+        """y = A_s(k) x (``hhg_apply_scaled``)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        prec, px, pk, py = self._vec_args(x, k, y)
+        L.check(self._lib.hhg_apply_scaled(self._h, prec, px, pk, py, _stream_ptr(stream)))
+        return y
+
+    def apply_onthefly(self, x, k, y=None, stream=None):
+        """y = A_n(k) x (``hhg_apply_onthefly``)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        prec, px, pk, py = self._vec_args(x, k, y)
+        L.check(self._lib.hhg_apply_onthefly(self._h, prec, px, pk, py, _stream_ptr(stream)))
+        return y
+
+    def residual(self, f, x, k, r=None, method="scaled", stream=None):
+        """r = f - A x (``hhg_residual``)."""
+        import torch
+        if r is None:
+            r = torch.empty_like(x)
+        prec, px, pk, pr = self._vec_args(x, k, r)
+        pf = _dev_ptr(f, (3, self.n_nodes), x.dtype)
+        m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
+        L.check(self._lib.hhg_residual(self._h, prec, m, pf, px, pk, pr, _stream_ptr(stream)))
+        return r
+
+    # ------------------------------------------------------------ tracing
+    def profile_enable(self, on=True):
+        L.check(self._lib.hhg_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since profiling was enabled."""
+        out = {}
+        for kid, name in L.KERNEL_NAMES.items():
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            L.check(self._lib.hhg_profile_read(self._h, kid, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (int(n.value), float(ms.value))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hhg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
