@@ -9,11 +9,12 @@
 // fixed by the zero row sum.  Opposite directions share Shat, so the
 // symmetric part needs 7 instead of 14 block products.
 //
-// Work decomposition: a workgroup owns CHUNK consecutive positions of the
+// Work decomposition: a workgroup owns TPB consecutive positions of the
 // in-plane layout (the same positions in every plane) and marches over a
 // range of planes.  The positions +-1 and +-(s+1..s+2) around the chunk are
 // staged, for planes k-1, k, k+1, in a rolling LDS buffer of (x0, x1, x2, k)
-// records, loaded with coalesced reads; Dirichlet values of x are zeroed while
+// records (two arrays of (x0, x1) and (x2, k) pairs), loaded with coalesced
+// reads one plane ahead of the computation; Dirichlet values of x are zeroed while
 // staging.  On-the-fly nodal integration (eq. nodalintegration) uses the same
 // staging and loops over the 24 elements of the node.
 #include <algorithm>
@@ -23,8 +24,14 @@
 namespace hhg {
 
 template <typename T>
-struct alignas(sizeof(T) * 4) Node4 {
+struct Node4 {
   T x0, x1, x2, k;
+};
+// LDS records: (x0, x1) and (x2, k) in two arrays, so that consecutive lanes
+// read consecutive 2*sizeof(T) records without bank conflicts.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T a, b;
 };
 
 __device__ __forceinline__ int tri_root_dev(int p) {
@@ -41,7 +48,6 @@ __device__ __forceinline__ int zero_set(int i, int j, int k, int n) {
 
 constexpr int METHOD_SCALED = 0;
 constexpr int METHOD_ONTHEFLY = 1;
-constexpr int MAX_WIN_PER_THREAD = (CHUNK + 2 * (1 << MAX_LEVEL) + 4 + CHUNK - 1) / CHUNK;
 
 template <typename T>
 __device__ __forceinline__ void sym_mv_acc(const T *S, T z0, T z1, T z2, T &y0, T &y1, T &y2) {
@@ -58,20 +64,22 @@ __device__ __forceinline__ void cross_acc(T w0, T w1, T w2, T d0, T d1, T d2, T 
   y2 = fma(w0, d1, fma(-w1, d0, y2));
 }
 
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
-__global__ __launch_bounds__(CHUNK) void k_interior(
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+__global__ __launch_bounds__(TPB) void k_interior(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
     T *__restrict__ y, int64_t nn, int wl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Node4<T> *buf = reinterpret_cast<Node4<T> *>(smem_raw);
+  Pair<T> *bufA = reinterpret_cast<Pair<T> *>(smem_raw);   // 3 planes of (x0, x1)
+  Pair<T> *bufB = bufA + 3 * wl;                             // 3 planes of (x2, k)
 
   const WorkItem w = work[blockIdx.x];
+  if (w.macro < 0) return;                  // padding item of the XCD-aware order
   const MacroInfo mi = minfo[w.macro];
   const int n = mi.n;
   const int tid = threadIdx.x;
-  const int p0 = w.chunk * CHUNK;
+  const int p0 = w.chunk * TPB;
   const int p = p0 + tid;
   const int s = tri_root_dev(p);
   const int i = p - s * (s + 1) / 2;
@@ -80,10 +88,10 @@ __global__ __launch_bounds__(CHUNK) void k_interior(
   const int ws = max(0, p0 - s_lo - 1);
 
   // anti-diagonal / position of the window entries this thread stages
-  int es[MAX_WIN_PER_THREAD], ei[MAX_WIN_PER_THREAD];
+  int es[NW], ei[NW];
 #pragma unroll
-  for (int r = 0; r < MAX_WIN_PER_THREAD; ++r) {
-    const int q = ws + tid + r * CHUNK;
+  for (int r = 0; r < NW; ++r) {
+    const int q = ws + tid + r * TPB;
     const int sq = tri_root_dev(q);
     es[r] = sq;
     ei[r] = q - sq * (sq + 1) / 2;
@@ -94,51 +102,77 @@ __global__ __launch_bounds__(CHUNK) void k_interior(
   const T *X2 = X1 + nn;
   const T *K = kc + mi.off;
 
-  auto stage = [&](int kk) {
-    Node4<T> *dst = buf + (kk % 3) * wl;
+  // plane kk of the window: global -> registers (Dirichlet values of x zeroed)
+  Node4<T> pre[NW];
+  auto fetch = [&](int kk) {
     const int ps = (int)tri(n + 1 - kk);
     const int64_t base = plane_base(n, kk);
 #pragma unroll
-    for (int r = 0; r < MAX_WIN_PER_THREAD; ++r) {
-      const int e = tid + r * CHUNK;
+    for (int r = 0; r < NW; ++r) {
+      const int e = tid + r * TPB;
+      const int q = ws + e;
+      Node4<T> v;
+      v.x0 = v.x1 = v.x2 = v.k = T(0);
+      if (e < wl && q < ps) {
+        const int64_t g = base + q;
+        v.x0 = X0[g];
+        v.x1 = X1[g];
+        v.x2 = X2[g];
+        v.k = K[g];
+        const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
+        if ((mi.dmask >> z) & 1u) v.x0 = v.x1 = v.x2 = T(0);
+      }
+      pre[r] = v;
+    }
+  };
+  // registers -> LDS slot of plane kk
+  auto put = [&](int kk) {
+    Pair<T> *da = bufA + (kk % 3) * wl;
+    Pair<T> *db = bufB + (kk % 3) * wl;
+#pragma unroll
+    for (int r = 0; r < NW; ++r) {
+      const int e = tid + r * TPB;
       if (e < wl) {
-        const int q = ws + e;
-        Node4<T> v;
-        if (q < ps) {
-          const int64_t g = base + q;
-          v.x0 = X0[g];
-          v.x1 = X1[g];
-          v.x2 = X2[g];
-          v.k = K[g];
-          const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
-          if ((mi.dmask >> z) & 1u) v.x0 = v.x1 = v.x2 = T(0);
-        } else {
-          v.x0 = v.x1 = v.x2 = v.k = T(0);
-        }
-        dst[e] = v;
+        da[e] = Pair<T>{pre[r].x0, pre[r].x1};
+        db[e] = Pair<T>{pre[r].x2, pre[r].k};
       }
     }
   };
 
-  stage(w.ka - 1);
-  stage(w.ka);
+  fetch(w.ka - 1);
+  put(w.ka - 1);
+  fetch(w.ka);
+  put(w.ka);
+  fetch(w.ka + 1);
+  put(w.ka + 1);
+  __syncthreads();
   const int e0 = p - ws;
   const bool col_ok = (s >= 2) && (i >= 1) && (j >= 1);
 
   for (int kk = w.ka; kk < w.kb; ++kk) {
-    stage(kk + 1);
-    __syncthreads();
+    // the plane needed by the next step is loaded while this one computes
+    const bool more = kk + 2 <= w.kb;
+    if (more) fetch(kk + 2);
     if (col_ok && s + kk <= n - 1) {
-      const Node4<T> *Pm = buf + ((kk + 2) % 3) * wl;  // plane kk-1
-      const Node4<T> *P0 = buf + (kk % 3) * wl;
-      const Node4<T> *Pp = buf + ((kk + 1) % 3) * wl;
-      const Node4<T> c = P0[e0];
+      const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
+      const int o0 = (kk % 3) * wl + e0;
+      const int op = ((kk + 1) % 3) * wl + e0;
+      auto rd = [&](int o) {
+        const Pair<T> a = bufA[o], b = bufB[o];
+        return Node4<T>{a.a, a.b, b.a, b.b};
+      };
+      const Node4<T> c = rd(o0);
       Node4<T> nb[NDIR];
 #pragma unroll
       for (int d = 0; d < NDIR; ++d) {
-        const Node4<T> *P = DIR_K[d] > 0 ? Pp : (DIR_K[d] < 0 ? Pm : P0);
-        nb[d] = P[e0 + dir_a(d) + dir_b(d) * s];
+        const int o = DIR_K[d] > 0 ? op : (DIR_K[d] < 0 ? om : o0);
+        nb[d] = rd(o + dir_a(d) + dir_b(d) * s);
       }
+      // LDS reads and the scalar loads of the stencil constants share one
+      // wait counter: take all neighbour records before any constant load
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+      __builtin_amdgcn_sched_barrier(0);
       T y0 = T(0), y1 = T(0), y2 = T(0);
       if constexpr (METHOD == METHOD_SCALED) {
         const StencilConst<T> &sc = scs[w.macro];
@@ -151,9 +185,9 @@ __global__ __launch_bounds__(CHUNK) void k_interior(
             const int d = 2 * pr + h;
             const int np = DIR_NT[d] == 6 ? 3 : 2;
             const T dx0 = nb[d].x0 - c.x0, dx1 = nb[d].x1 - c.x1, dx2 = nb[d].x2 - c.x2;
-            T ring = T(0);
+            T ring = nb[RING_V[d][0]].k + nb[RING_VM[d][0]].k;
 #pragma unroll
-            for (int q = 0; q < np; ++q) ring += nb[RING_V[d][q]].k + nb[RING_VM[d][q]].k;
+            for (int q = 1; q < np; ++q) ring += nb[RING_V[d][q]].k + nb[RING_VM[d][q]].k;
             const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
             const T kh = fma(sc.w_end, c.k + nb[d].k, wr * ring);
             z0 = fma(kh, dx0, z0);
@@ -218,6 +252,8 @@ __global__ __launch_bounds__(CHUNK) void k_interior(
       y[g + 2 * nn] = y2;
     }
     __syncthreads();
+    if (more) put(kk + 2);               // overwrites the slot of plane kk-1
+    __syncthreads();
   }
 }
 
@@ -225,29 +261,33 @@ __global__ __launch_bounds__(CHUNK) void k_interior(
 // computes the partial row of its macro; copies are summed afterwards.
 // ROWWISE: nodal integration for the whole row (also the on-the-fly method);
 // otherwise scaled entries towards macro-interior neighbours and nodal
-// entries towards macro-boundary neighbours and on the diagonal.
+// entries towards macro-boundary neighbours and on the diagonal.  Every block
+// holds nodes of one macro, so the macro's constants are uniform loads.
+__device__ __forceinline__ int plane_base32(int n, int k) {
+  const int a = n + 1, b = n + 1 - k;
+  return a * (a + 1) * (a + 2) / 6 - b * (b + 1) * (b + 2) / 6;
+}
+
 template <typename T, bool RESID, bool ROWWISE, bool CORR>
-__global__ __launch_bounds__(256) void k_boundary_rows(
+__global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
-    const ElemConst<T> *__restrict__ ecs, const int2 *__restrict__ bslot,
-    const uint8_t *__restrict__ flags, int64_t nb, const T *__restrict__ x,
-    const T *__restrict__ kc, const T *__restrict__ f, T *__restrict__ y, int64_t nn) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nb) return;
-  const int2 b = bslot[idx];
-  const MacroInfo mi = minfo[b.x];
+    const ElemConst<T> *__restrict__ ecs, const int32_t *__restrict__ bijk,
+    const int32_t *__restrict__ bblk, const uint8_t *__restrict__ flags,
+    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
+    T *__restrict__ y, int64_t nn) {
+  const int m = bblk[blockIdx.x];
+  const int packed = bijk[(int64_t)blockIdx.x * BOUNDARY_BLOCK + threadIdx.x];
+  if (packed < 0) return;
+  const MacroInfo mi = minfo[m];
   const int n = mi.n;
-  const int i = b.y & 1023, j = (b.y >> 10) & 1023, k = (b.y >> 20) & 1023;
-  const int64_t slot = mi.off + plane_base(n, k) + tri(i + j) + i;
-  const int z0 = zero_set(i, j, k, n);
-  if ((mi.dmask >> z0) & 1u) {
-    y[slot] = T(0);
-    y[slot + nn] = T(0);
-    y[slot + 2 * nn] = T(0);
-    return;
-  }
-  // neighbour data (slot, inside, on boundary, Dirichlet)
-  int64_t ns[NDIR];
+  const int i = packed & 1023, j = (packed >> 10) & 1023, k = (packed >> 20) & 1023;
+  const T *X0 = x + mi.off;
+  const T *X1 = X0 + nn;
+  const T *X2 = X1 + nn;
+  const T *KC = kc + mi.off;
+  const int lslot = plane_base32(n, k) + (i + j) * (i + j + 1) / 2 + i;
+  const int64_t slot = mi.off + lslot;
+  // neighbour data (inside the macro, on its boundary, Dirichlet-masked x)
   bool in[NDIR], onb[NDIR];
   T nx0[NDIR], nx1[NDIR], nx2[NDIR], nk[NDIR];
 #pragma unroll
@@ -256,22 +296,21 @@ __global__ __launch_bounds__(256) void k_boundary_rows(
     in[d] = a >= 0 && bb >= 0 && cc >= 0 && a + bb + cc <= n;
     onb[d] = false;
     nx0[d] = nx1[d] = nx2[d] = nk[d] = T(0);
-    ns[d] = 0;
     if (in[d]) {
       const int zz = zero_set(a, bb, cc, n);
       onb[d] = zz != 0;
-      ns[d] = mi.off + plane_base(n, cc) + tri(a + bb) + a;
-      nk[d] = kc[ns[d]];
+      const int ls = plane_base32(n, cc) + (a + bb) * (a + bb + 1) / 2 + a;
+      nk[d] = KC[ls];
       if (!((mi.dmask >> zz) & 1u)) {
-        nx0[d] = x[ns[d]];
-        nx1[d] = x[ns[d] + nn];
-        nx2[d] = x[ns[d] + 2 * nn];
+        nx0[d] = X0[ls];
+        nx1[d] = X1[ls];
+        nx2[d] = X2[ls];
       }
     }
   }
-  const T ci0 = x[slot], ci1 = x[slot + nn], ci2 = x[slot + 2 * nn];
-  const T ck = kc[slot];
-  const ElemConst<T> &ec = ecs[b.x];
+  const T ci0 = X0[lslot], ci1 = X1[lslot], ci2 = X2[lslot];
+  const T ck = KC[lslot];
+  const ElemConst<T> &ec = ecs[m];
   T y0 = T(0), y1 = T(0), y2 = T(0);
 #pragma unroll
   for (int t = 0; t < NTET; ++t) {
@@ -296,7 +335,7 @@ __global__ __launch_bounds__(256) void k_boundary_rows(
     }
   }
   if (!ROWWISE) {
-    const StencilConst<T> &sc = scs[b.x];
+    const StencilConst<T> &sc = scs[m];
 #pragma unroll
     for (int d = 0; d < NDIR; ++d) {
       if (!in[d] || onb[d]) continue;
@@ -335,21 +374,26 @@ __global__ __launch_bounds__(256) void k_boundary_rows(
   y[slot + 2 * nn] = y2;
 }
 
-// Sum of the partial rows of all copies of an interface node; the total
-// (or f minus it) is written to every copy, keeping the output consistent.
+// Sum of the partial rows of all copies of an interface node; the total (or
+// f minus it) is written to every copy, keeping the output consistent.
+// Threads past the groups write the zero rows of the Dirichlet slots.
 template <typename T, bool RESID>
-__global__ __launch_bounds__(256) void k_group_sum(const int64_t *__restrict__ ptr,
-                                                   const int64_t *__restrict__ slots, int64_t ng,
-                                                   const T *__restrict__ f, T *__restrict__ y,
-                                                   int64_t nn) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ng) return;
-  const int64_t a = ptr[g], b = ptr[g + 1];
-  for (int c = 0; c < 3; ++c) {
+__global__ __launch_bounds__(256) void k_finish(const int64_t *__restrict__ ptr,
+                                                const int64_t *__restrict__ slots, int64_t ng,
+                                                const int64_t *__restrict__ dslot, int64_t nd,
+                                                const T *__restrict__ f, T *__restrict__ y,
+                                                int64_t nn) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (item, component)
+  const int64_t g = t / 3;
+  const int c = (int)(t - 3 * g);
+  if (g < ng) {
+    const int64_t a = ptr[g], b = ptr[g + 1];
     T sum = T(0);
     for (int64_t q = a; q < b; ++q) sum += y[c * nn + slots[q]];
     if (RESID) sum = f[c * nn + slots[a]] - sum;
     for (int64_t q = a; q < b; ++q) y[c * nn + slots[q]] = sum;
+  } else if (g - ng < nd) {
+    y[c * nn + dslot[g - ng]] = T(0);
   }
 }
 
@@ -369,21 +413,34 @@ const ElemConst<double> *ec_ptr<double>(hhg_ctx *h) { return h->d_ec64; }
 template <>
 const ElemConst<float> *ec_ptr<float>(hhg_ctx *h) { return h->d_ec32; }
 
-int window_len(hhg_ctx *h) { return CHUNK + 2 * (1 << h->max_level) + 4; }
-
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
-int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
-  if (h->n_work == 0) return HHG_OK;
-  const int wl = window_len(h);
-  const size_t lds = 3 * (size_t)wl * sizeof(Node4<T>);
-  auto kern = k_interior<T, METHOD, RESID, CORR, A0>;
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
+  const int wl = h->wl_max;
+  const size_t lds = 6 * (size_t)wl * sizeof(Pair<T>);
+  auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB>;
   if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
-  hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(CHUNK), lds, st, h->d_minfo, sc_ptr<T>(h),
+  hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
                      ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
   HHG_HIP(hipGetLastError());
   return HHG_OK;
+}
+
+// Positions per work item (= threads): 256 or 512; window entries per
+// thread: up to 2 (levels <= 7 with 256, <= 8 with 512) or up to 6.
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
+int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
+  if (h->n_work == 0) return HHG_OK;
+  const int nw = (h->wl_max + h->chunk - 1) / h->chunk;
+  if (h->chunk == 256) {
+    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256>(h, x, k, f, y, st);
+    if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256>(h, x, k, f, y, st);
+  } else if (h->chunk == 512) {
+    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 512>(h, x, k, f, y, st);
+    if (nw <= 3) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 3, 512>(h, x, k, f, y, st);
+  }
+  return fail(HHG_EINVAL, "interior window larger than supported");
 }
 
 template <typename T, int METHOD, bool RESID>
@@ -399,15 +456,14 @@ int launch_interior_v(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipS
 template <typename T, bool RESID>
 int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, T *y,
                     hipStream_t st) {
-  if (h->n_bslot == 0) return HHG_OK;
   const bool rowwise = method == METHOD_ONTHEFLY || h->op.iface == HHG_IFACE_ROWWISE;
   const bool corr = h->op.corr == HHG_CORR_PHYSICAL;
-  const dim3 grid((unsigned)((h->n_bslot + 255) / 256));
-#define HHG_LB(RW, CR)                                                                          \
-  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR>), grid, dim3(256), 0, st, h->d_minfo,  \
-                     sc_ptr<T>(h), ec_ptr<T>(h), h->d_bslot, h->d_flags, h->n_bslot, x, k, f, y, \
-                     h->n_nodes)
-  {
+  if (!h->bblk.empty()) {
+    const dim3 grid((unsigned)h->bblk.size());
+#define HHG_LB(RW, CR)                                                                           \
+  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR>), grid, dim3(BOUNDARY_BLOCK), 0, st,    \
+                     h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_bijk, h->d_bblk, h->d_flags, x, \
+                     k, f, y, h->n_nodes)
     ProfScope prof(h, HHG_K_BOUNDARY_ROWS, st);
     if (rowwise)
       HHG_LB(true, false);
@@ -415,32 +471,41 @@ int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, 
       HHG_LB(false, true);
     else
       HHG_LB(false, false);
-  }
 #undef HHG_LB
-  HHG_HIP(hipGetLastError());
-  if (h->n_grp > 0) {
-    const dim3 g2((unsigned)((h->n_grp + 255) / 256));
+    HHG_HIP(hipGetLastError());
+  }
+  const int64_t nd = (int64_t)h->dslot.size();
+  const int64_t total = 3 * (h->n_grp + nd);
+  if (total > 0) {
+    const dim3 g2((unsigned)((total + 255) / 256));
     ProfScope prof(h, HHG_K_GROUP_SUM, st);
-    hipLaunchKernelGGL((k_group_sum<T, RESID>), g2, dim3(256), 0, st, h->d_grp_ptr, h->d_grp_slot,
-                       h->n_grp, f, y, h->n_nodes);
+    hipLaunchKernelGGL((k_finish<T, RESID>), g2, dim3(256), 0, st, h->d_grp_ptr, h->d_grp_slot,
+                       h->n_grp, h->d_dslot, nd, f, y, h->n_nodes);
     HHG_HIP(hipGetLastError());
   }
   return HHG_OK;
 }
 
+// Interior rows run on the caller's stream, macro-boundary rows and the copy
+// sums on the handle's side stream (they write disjoint slots), joined back
+// before the call's work is complete on the caller's stream.
 template <typename T>
 int apply_t(hhg_ctx *h, int method, const T *f, const T *x, const T *k, T *y, hipStream_t st) {
+  HHG_HIP(hipEventRecord(h->ev_fork, st));
+  HHG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
   int rc;
   if (f) {
     rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, true>(h, x, k, f, y, st)
                                  : launch_interior_v<T, METHOD_ONTHEFLY, true>(h, x, k, f, y, st);
-    if (rc) return rc;
-    return launch_boundary<T, true>(h, method, x, k, f, y, st);
+    if (!rc) rc = launch_boundary<T, true>(h, method, x, k, f, y, h->side);
+  } else {
+    rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, st)
+                                 : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, st);
+    if (!rc) rc = launch_boundary<T, false>(h, method, x, k, f, y, h->side);
   }
-  rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, st)
-                               : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, st);
-  if (rc) return rc;
-  return launch_boundary<T, false>(h, method, x, k, f, y, st);
+  HHG_HIP(hipEventRecord(h->ev_join, h->side));
+  HHG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));
+  return rc;
 }
 
 bool overlaps(const void *a, const void *b, size_t bytes) {

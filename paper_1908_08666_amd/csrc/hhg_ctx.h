@@ -22,9 +22,13 @@ struct hhg_ctx {
   std::vector<hhg::StencilConst<double>> sc64;
   std::vector<hhg::ElemConst<double>> ec64;
   std::vector<hhg::WorkItem> work;
-  std::vector<int2> bslot;
+  std::vector<int32_t> bijk;                 // non-Dirichlet boundary slots, packed (i,j,k)
+  std::vector<int32_t> bblk;                 // macro of each boundary-row block
+  std::vector<int64_t> dslot;                // Dirichlet slots (rows written as zero)
   std::vector<int64_t> grp_ptr, grp_slot;
-  int planes_per_item = 16;
+  int wl_max = 0;                            // LDS window entries per plane
+  int planes_per_item = 4;
+  int chunk = 256;                           // positions per interior work item
   bool on_device = false;                    // tables uploaded (first device call)
   int device = -1;
 
@@ -36,12 +40,15 @@ struct hhg_ctx {
   hhg::ElemConst<float> *d_ec32 = nullptr;
   hhg::WorkItem *d_work = nullptr;
   int n_work = 0;
-  int2 *d_bslot = nullptr;                   // (macro, packed i | j<<10 | k<<20)
-  int64_t n_bslot = 0;
+  int32_t *d_bijk = nullptr;
+  int32_t *d_bblk = nullptr;
+  int64_t *d_dslot = nullptr;
   int64_t *d_grp_ptr = nullptr;              // interface copy groups (>= 2 copies)
   int64_t *d_grp_slot = nullptr;
   int64_t n_grp = 0;
   uint8_t *d_flags = nullptr;
+  hipStream_t side = nullptr;                // macro-boundary rows run here
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // kernel timing (hhg_profile_*)
   struct ProfRec {

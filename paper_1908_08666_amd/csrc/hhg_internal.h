@@ -100,6 +100,7 @@ struct WorkItem {
   int32_t macro, chunk, ka, kb;
 };
 
-constexpr int CHUNK = 256;      // positions per interior work item (= threads)
+constexpr int BOUNDARY_BLOCK = 256;  // threads per block of the boundary-row kernel
+constexpr int NXCD = 8;              // accelerator complex dies of an MI355X
 
 }  // namespace hhg

@@ -318,27 +318,34 @@ struct KeyHash {
   }
 };
 
+template <typename P>
+void dfree(P *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
 void free_ctx(hhg_ctx *h) {
   if (!h) return;
-  if (!h->on_device) {
-    delete h;
-    return;
-  }
-  (void)hipFree(h->d_minfo);
-  (void)hipFree(h->d_sc64);
-  (void)hipFree(h->d_sc32);
-  (void)hipFree(h->d_ec64);
-  (void)hipFree(h->d_ec32);
-  (void)hipFree(h->d_work);
-  (void)hipFree(h->d_bslot);
-  (void)hipFree(h->d_grp_ptr);
-  (void)hipFree(h->d_grp_slot);
-  (void)hipFree(h->d_flags);
+  dfree(h->d_minfo);
+  dfree(h->d_sc64);
+  dfree(h->d_sc32);
+  dfree(h->d_ec64);
+  dfree(h->d_ec32);
+  dfree(h->d_work);
+  dfree(h->d_bijk);
+  dfree(h->d_bblk);
+  dfree(h->d_dslot);
+  dfree(h->d_grp_ptr);
+  dfree(h->d_grp_slot);
+  dfree(h->d_flags);
   for (auto &r : h->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->side) (void)hipStreamDestroy(h->side);
   delete h;
 }
 
@@ -454,7 +461,7 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
 
   // -------------------------------------------- slots: flags and groups
   h->flags.assign((size_t)h->n_nodes, 0);
-  std::vector<int2> bslot;
+  std::vector<int2> bslot;          // all boundary slots (macro, packed i | j<<10 | k<<20)
   std::unordered_map<std::array<int64_t, 6>, std::vector<int64_t>, KeyHash> groups;
   for (int m = 0; m < M; ++m) {
     const int n = h->minfo[m].n;
@@ -521,6 +528,30 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
     }
   }
   h->n_grp = (int64_t)gptr.size() - 1;
+  // boundary-row kernel input: non-Dirichlet boundary slots grouped by macro,
+  // each macro padded to whole blocks so that a block sees a single macro
+  std::vector<int32_t> bijk, bblk;
+  std::vector<int64_t> dslot;
+  {
+    size_t q = 0;
+    for (int m = 0; m < M; ++m) {
+      size_t cnt = 0;
+      for (; q < bslot.size() && bslot[q].x == m; ++q) {
+        const int n = h->minfo[m].n;
+        const int i = bslot[q].y & 1023, j = (bslot[q].y >> 10) & 1023, k = (bslot[q].y >> 20) & 1023;
+        const int64_t slot = h->minfo[m].off + plane_base(n, k) + tri(i + j) + i;
+        if (h->flags[slot] & 1) {
+          dslot.push_back(slot);
+          continue;
+        }
+        bijk.push_back(bslot[q].y);
+        ++cnt;
+      }
+      const size_t pad = (BOUNDARY_BLOCK - cnt % BOUNDARY_BLOCK) % BOUNDARY_BLOCK;
+      for (size_t r = 0; r < pad; ++r) bijk.push_back(-1);
+      for (size_t r = 0; r < (cnt + pad) / BOUNDARY_BLOCK; ++r) bblk.push_back(m);
+    }
+  }
   int64_t nu = 0;
   for (uint8_t f : h->flags) nu += ((f & 2) && !(f & 1)) ? 1 : 0;
   h->n_unknown = nu;
@@ -528,23 +559,50 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   // --------------------------------------------------- interior work list
   const char *env = std::getenv("HHG_PLANES_PER_ITEM");
   if (env) h->planes_per_item = std::max(1, std::atoi(env));
+  const char *envc = std::getenv("HHG_CHUNK");
+  h->chunk = (envc && std::atoi(envc) == 512) ? 512 : 256;
+  // a 512-position window beyond level 8 needs more than 3 entries per thread
+  if (h->max_level > 8) h->chunk = 256;
+  const int CH = h->chunk;
+  std::vector<WorkItem> natural;
+  int wl_max = 0;
   for (int m = 0; m < M; ++m) {
     const int n = h->minfo[m].n;
     const int64_t npos = tri(n - 1);  // interior positions live below T(n-1)
-    const int nchunk = (int)((npos + CHUNK - 1) / CHUNK);
+    const int nchunk = (int)((npos + CH - 1) / CH);
+    std::vector<int> kmax(nchunk);
+    int kmax_all = 0;
     for (int c = 0; c < nchunk; ++c) {
-      const int64_t s_lo = std::max<int64_t>(2, tri_root((int64_t)c * CHUNK));
-      const int kmax = (int)(n - 1 - s_lo);
-      for (int ka = 1; ka <= kmax; ka += h->planes_per_item)
-        h->work.push_back({m, c, ka, std::min(ka + h->planes_per_item, kmax + 1)});
+      const int64_t p0 = (int64_t)c * CH;
+      const int64_t s_lo = tri_root(p0);
+      const int64_t s_hi = std::min<int64_t>(tri_root(p0 + CH - 1), n - 2);
+      const int64_t ws = std::max<int64_t>(0, p0 - s_lo - 1);
+      wl_max = std::max<int>(wl_max, (int)(p0 + CH - 1 + s_hi + 2 - ws + 1));
+      kmax[c] = (int)(n - 1 - std::max<int64_t>(2, s_lo));
+      kmax_all = std::max(kmax_all, kmax[c]);
+    }
+    for (int ka = 1; ka <= kmax_all; ka += h->planes_per_item)
+      for (int c = 0; c < nchunk; ++c)
+        if (ka <= kmax[c]) natural.push_back({m, c, ka, std::min(ka + h->planes_per_item, kmax[c] + 1)});
+  }
+  h->wl_max = wl_max;
+  // workgroup g runs on XCD g % NXCD: give every XCD a contiguous stretch of
+  // the natural order so that neighbouring chunks share its L2
+  {
+    const size_t per = (natural.size() + NXCD - 1) / NXCD;
+    h->work.assign(per * NXCD, WorkItem{-1, 0, 0, 0});
+    for (size_t q = 0; q < natural.size(); ++q) {
+      const size_t x = q / per, r = q % per;
+      h->work[r * NXCD + x] = natural[q];
     }
   }
   h->n_work = (int)h->work.size();
 
-  h->bslot = std::move(bslot);
+  h->bijk = std::move(bijk);
+  h->bblk = std::move(bblk);
+  h->dslot = std::move(dslot);
   h->grp_ptr = std::move(gptr);
   h->grp_slot = std::move(gslot);
-  h->n_bslot = (int64_t)h->bslot.size();
   return HHG_OK;
 }
 
@@ -559,6 +617,7 @@ int ensure_device(hhg_ctx *h) {
     return HHG_OK;
   }
   const int M = h->n_macro;
+  h->device = dev;
   std::vector<StencilConst<float>> sc32(M);
   std::vector<ElemConst<float>> ec32(M);
   for (int m = 0; m < M; ++m) {
@@ -572,10 +631,15 @@ int ensure_device(hhg_ctx *h) {
   if ((rc = upload(&h->d_ec64, h->ec64.data(), M))) return rc;
   if ((rc = upload(&h->d_ec32, ec32.data(), M))) return rc;
   if ((rc = upload(&h->d_work, h->work.data(), h->work.size()))) return rc;
-  if ((rc = upload(&h->d_bslot, h->bslot.data(), h->bslot.size()))) return rc;
+  if ((rc = upload(&h->d_bijk, h->bijk.data(), h->bijk.size()))) return rc;
+  if ((rc = upload(&h->d_bblk, h->bblk.data(), h->bblk.size()))) return rc;
+  if ((rc = upload(&h->d_dslot, h->dslot.data(), h->dslot.size()))) return rc;
   if ((rc = upload(&h->d_grp_ptr, h->grp_ptr.data(), h->grp_ptr.size()))) return rc;
   if ((rc = upload(&h->d_grp_slot, h->grp_slot.data(), h->grp_slot.size()))) return rc;
   if ((rc = upload(&h->d_flags, h->flags.data(), h->flags.size()))) return rc;
+  HHG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  HHG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  HHG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
   h->on_device = true;
   h->device = dev;
   return HHG_OK;
