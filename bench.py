@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--solve", action="store_true", help="also time CG / IR solves to 1e-8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
@@ -151,7 +152,7 @@ def main():
 
     extra = {}
     if args.extra:
-        del sets64
+        sets64 = None
         torch.cuda.empty_cache()
         sets64 = make_sets(torch.float64)
         t_fly, p_fly = timed(lambda x, k, y: mesh.apply_onthefly(x, k, y), sets64,
@@ -162,7 +163,7 @@ def main():
         t_res, _ = timed(lambda x, k, y: mesh.residual(x, x, k, y), sets64, max(args.steps // 4, 5),
                          5, profile=False)
         extra["residual_f64_MDoF_s"] = round(dofs / (t_res / max(args.steps // 4, 5) * 1e-3) / 1e6, 1)
-        del sets64
+        sets64 = None
         torch.cuda.empty_cache()
         sets32 = make_sets(torch.float32)
         t32, p32 = timed(lambda x, k, y: mesh.apply_scaled(x, k, y), sets32, args.steps, args.warmup)
@@ -171,6 +172,34 @@ def main():
         a32 = BYTES_PER_INTERIOR_NODE["f32"] * interior_rows / (ms / max(c, 1) * 1e-3) / 1e9
         extra["scaled_f32_interior_avg_ms"] = round(ms / max(c, 1), 5)
         extra["scaled_f32_interior_GBs"] = round(a32, 1)
+
+    if args.solve:
+        sets64 = sets32 = None
+        torch.cuda.empty_cache()
+        b = torch.from_numpy(consistent_random(mesh, W.rng_for(2, 99), 3)).to(dev, torch.float64)
+        fl = torch.from_numpy(mesh.flags()).to(dev)
+        b[:, (fl & 1) > 0] = 0.0
+        k64 = torch.from_numpy(k_np).to(dev, torch.float64)
+        solves = {}
+        ws = None
+        for name, opts in (("cg64", dict(solver="cg64")),
+                           ("ir32_inner1e-2", dict(solver="ir32", inner_rtol=1e-2)),
+                           ("ir32_inner1e-3", dict(solver="ir32", inner_rtol=1e-3)),
+                           ("ir32_inner1e-4", dict(solver="ir32", inner_rtol=1e-4))):
+            nbytes = mesh.workspace_bytes(**opts)
+            if ws is None or ws.numel() < nbytes + 256:
+                ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            for rep in range(2):          # second run reuses the warmed state
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = mesh.solve(b, k64, x=x, workspace=ws, rtol=1e-8, check_every=16, **opts)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+            solves[name] = dict(iterations=info["iterations"], outer=info["outer_iterations"],
+                                seconds=round(wall, 4), rel_residual=info["rel_residual"],
+                                status=info["status"])
+        extra["solve_to_1e-8"] = solves
 
     cpu = None
     if not args.no_cpu_baseline:

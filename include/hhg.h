@@ -157,17 +157,68 @@ int hhg_apply_onthefly(hhg_handle h, int32_t prec, const void *x, const void *k,
 int hhg_residual(hhg_handle h, int32_t prec, int32_t method, const void *f, const void *x,
                  const void *k, void *r, void *stream);
 
+/* Solvers for A x = b on the unknowns (distinct non-Dirichlet nodes); the
+ * paper solves these systems by multigrid (Sec. 5), this library provides
+ * Krylov solvers over the same operators:
+ *   HHG_CG_F64  preconditioned CG, all vectors, dots and applies in FP64.
+ *   HHG_IR_F32  iterative refinement: the residual b - A x, its norm and the
+ *               update x += e in FP64; the correction e from an inner
+ *               preconditioned CG with FP32 vectors, FP32 coefficient and
+ *               FP32 applies, inner dot products accumulated in FP64, run to
+ *               inner_rtol relative reduction.
+ * Preconditioner: HHG_PRECOND_NONE, or HHG_PRECOND_BLOCK_JACOBI (inverse of
+ * the 3x3 diagonal block of the assembled operator at every node).
+ * Stopping rule: ||b - A x||_2 <= rtol ||b||_2 over the unknowns, with the
+ * final residual recomputed in FP64 (reported in info->rel_residual). */
+enum hhg_solver { HHG_CG_F64 = 0, HHG_IR_F32 = 1 };
+enum hhg_precond { HHG_PRECOND_NONE = 0, HHG_PRECOND_BLOCK_JACOBI = 1 };
+
+typedef struct {
+  int32_t solver;        /* hhg_solver                                        */
+  int32_t precond;       /* hhg_precond                                       */
+  int32_t method;        /* HHG_METHOD_SCALED or HHG_METHOD_ONTHEFLY operator */
+  int32_t maxit;         /* total CG iterations allowed (inner ones for IR)   */
+  double rtol;           /* relative residual target, e.g. 1e-8               */
+  double inner_rtol;     /* IR: relative reduction per inner solve, e.g. 1e-3 */
+  int32_t check_every;   /* iterations between host convergence checks (>= 1) */
+  int32_t pad;
+} hhg_solve_opts;
+
+typedef struct {
+  int32_t iterations;        /* CG iterations (all inner iterations for IR)   */
+  int32_t outer_iterations;  /* IR refinement steps (1 for CG_F64)            */
+  int32_t status;            /* HHG_OK, HHG_ENOCONV or HHG_EBREAKDOWN         */
+  int32_t pad;
+  double rel_residual;       /* ||b - A x|| / ||b|| recomputed in FP64        */
+  double seconds;            /* wall time of the solve                        */
+} hhg_solve_info;
+
+/* Device workspace needed by hhg_cg_solve for these options (bytes).      */
+int hhg_workspace_bytes(hhg_handle h, const hhg_solve_opts *o, size_t *bytes);
+
+/* Solve A x = b.  b, k, x: FP64 device vectors ([3][n], [n], [3][n]); x is
+ * the start vector on input and the solution on output; b must be consistent
+ * (its Dirichlet entries are ignored).  workspace: device memory of
+ * hhg_workspace_bytes, 256-byte aligned, owned by the caller.  Runs on
+ * `stream` and synchronizes it before returning.  Returns HHG_OK,
+ * HHG_ENOCONV (maxit reached; x and info written), HHG_EBREAKDOWN (NaN/Inf
+ * or p^T A p <= 0: indefinite operator or corrupt input), HHG_EINVAL. */
+int hhg_cg_solve(hhg_handle h, const hhg_solve_opts *o, const double *b, const double *k,
+                 double *x, void *workspace, hhg_solve_info *info, void *stream);
+
 /* Kernel timing (tracing aid, not needed for results).  While enabled,
  * every kernel the library launches is bracketed by a pair of HIP events on
  * the launch stream.  hhg_profile_read synchronizes those events and returns,
  * per kernel id, the number of launches and the summed duration in ms since
  * enabling; ids: 0 interior scaled apply, 1 interior on-the-fly apply,
- * 2 macro-boundary rows, 3 copy-group sum.  Enabling resets the counters.    */
+ * 2 macro-boundary rows, 3 copy-group sum, 4 solver vector kernels.
+ * Enabling resets the counters.                                             */
 enum hhg_kernel_id {
   HHG_K_INTERIOR_SCALED = 0,
   HHG_K_INTERIOR_ONTHEFLY = 1,
   HHG_K_BOUNDARY_ROWS = 2,
   HHG_K_GROUP_SUM = 3,
+  HHG_K_SOLVER_VECTOR = 4,   /* all fused vector / reduction kernels of the solvers */
   HHG_K_COUNT = 16
 };
 int hhg_profile_enable(hhg_handle h, int32_t on);

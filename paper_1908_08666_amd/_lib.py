@@ -16,7 +16,8 @@ HHG_KHAT_PATCH, HHG_KHAT_EDGE = 0, 1
 HHG_IFACE_SYMMETRIC, HHG_IFACE_ROWWISE = 0, 1
 HHG_METHOD_SCALED, HHG_METHOD_ONTHEFLY = 0, 1
 HHG_K_INTERIOR_SCALED, HHG_K_INTERIOR_ONTHEFLY, HHG_K_BOUNDARY_ROWS, HHG_K_GROUP_SUM = 0, 1, 2, 3
-KERNEL_NAMES = {0: "interior_scaled", 1: "interior_onthefly", 2: "boundary_rows", 3: "group_sum"}
+KERNEL_NAMES = {0: "interior_scaled", 1: "interior_onthefly", 2: "boundary_rows", 3: "group_sum",
+                4: "solver_vector"}
 
 STATUS_NAMES = {0: "HHG_OK", -1: "HHG_EINVAL", -2: "HHG_EHIP", -3: "HHG_ENOCONV",
                 -4: "HHG_EBREAKDOWN", -5: "HHG_ENOMEM"}
@@ -32,6 +33,22 @@ class OpDesc(ctypes.Structure):
     _fields_ = [("mu0", ctypes.c_double), ("lam0", ctypes.c_double), ("mu1", ctypes.c_double),
                 ("lam1", ctypes.c_double), ("corr", ctypes.c_int32), ("khat", ctypes.c_int32),
                 ("iface", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("precond", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("outer_iterations", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+HHG_CG_F64, HHG_IR_F32 = 0, 1
+HHG_PRECOND_NONE, HHG_PRECOND_BLOCK_JACOBI = 0, 1
 
 
 class HHGError(RuntimeError):
@@ -55,6 +72,9 @@ SIGNATURES = {
     "hhg_apply_scaled": ([_VP, _I32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "hhg_apply_onthefly": ([_VP, _I32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "hhg_residual": ([_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_workspace_bytes": ([_VP, ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hhg_cg_solve": ([_VP, ctypes.POINTER(SolveOpts), _VP, _VP, _VP, _VP, ctypes.POINTER(SolveInfo), _VP],
+                     ctypes.c_int),
     "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hhg_last_error": ([], ctypes.c_char_p),

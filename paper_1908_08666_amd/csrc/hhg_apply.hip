@@ -1,261 +1,11 @@
-// Operator application kernels for gfx950.
-//
-// Interior rows (the hot path, Sec. 4: asymptotically all work is in macro
-// interiors): for every macro-interior node i
-//     y_i = sum_{d} S_{i,d} (x_{i+d} - x_i),
-//     S_{i,d} = A0_d + khat_{i,d} Shat_d + sum_{v in H_d} (k_v - k_{v^m}) C^v_d,
-// which is the Lemma (eqs. bilinearformscaling, patchmean, corrtermgeneral)
-// in the ring form of Sec. 2.4 (eq. correctionterm3D), with the centre entry
-// fixed by the zero row sum.  Opposite directions share Shat, so the
-// symmetric part needs 7 instead of 14 block products.
-//
-// Work decomposition: a workgroup owns TPB consecutive positions of the
-// in-plane layout (the same positions in every plane) and marches over a
-// range of planes.  The positions +-1 and +-(s+1..s+2) around the chunk are
-// staged, for planes k-1, k, k+1, in a rolling LDS buffer of (x0, x1, x2, k)
-// records (two arrays of (x0, x1) and (x2, k) pairs), loaded with coalesced
-// reads one plane ahead of the computation; Dirichlet values of x are zeroed while
-// staging.  On-the-fly nodal integration (eq. nodalintegration) uses the same
-// staging and loops over the 24 elements of the node.
+// Operator application: macro-boundary rows, copy sums, launch sequence
+// and the C ABI entry points.  The interior-row kernels (the hot path) live in
+// hhg_interior.h and are compiled per element type and method.
 #include <algorithm>
 
-#include "hhg_ctx.h"
+#include "hhg_device.h"
 
 namespace hhg {
-
-template <typename T>
-struct Node4 {
-  T x0, x1, x2, k;
-};
-// LDS records: (x0, x1) and (x2, k) in two arrays, so that consecutive lanes
-// read consecutive 2*sizeof(T) records without bank conflicts.
-template <typename T>
-struct alignas(2 * sizeof(T)) Pair {
-  T a, b;
-};
-
-__device__ __forceinline__ int tri_root_dev(int p) {
-  int s = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
-  if ((s + 1) * (s + 2) / 2 <= p) ++s;
-  if (s * (s + 1) / 2 > p) --s;
-  return s;
-}
-
-// barycentric zero set of node (i, j, k) in a macro with n intervals
-__device__ __forceinline__ int zero_set(int i, int j, int k, int n) {
-  return ((n - i - j - k) == 0) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3);
-}
-
-constexpr int METHOD_SCALED = 0;
-constexpr int METHOD_ONTHEFLY = 1;
-
-template <typename T>
-__device__ __forceinline__ void sym_mv_acc(const T *S, T z0, T z1, T z2, T &y0, T &y1, T &y2) {
-  // S = xx yy zz xy xz yz
-  y0 = fma(S[0], z0, fma(S[3], z1, fma(S[4], z2, y0)));
-  y1 = fma(S[3], z0, fma(S[1], z1, fma(S[5], z2, y1)));
-  y2 = fma(S[4], z0, fma(S[5], z1, fma(S[2], z2, y2)));
-}
-
-template <typename T>
-__device__ __forceinline__ void cross_acc(T w0, T w1, T w2, T d0, T d1, T d2, T &y0, T &y1, T &y2) {
-  y0 = fma(w1, d2, fma(-w2, d1, y0));
-  y1 = fma(w2, d0, fma(-w0, d2, y1));
-  y2 = fma(w0, d1, fma(-w1, d0, y2));
-}
-
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
-__global__ __launch_bounds__(TPB) void k_interior(
-    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
-    const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
-    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  Pair<T> *bufA = reinterpret_cast<Pair<T> *>(smem_raw);   // 3 planes of (x0, x1)
-  Pair<T> *bufB = bufA + 3 * wl;                             // 3 planes of (x2, k)
-
-  const WorkItem w = work[blockIdx.x];
-  if (w.macro < 0) return;                  // padding item of the XCD-aware order
-  const MacroInfo mi = minfo[w.macro];
-  const int n = mi.n;
-  const int tid = threadIdx.x;
-  const int p0 = w.chunk * TPB;
-  const int p = p0 + tid;
-  const int s = tri_root_dev(p);
-  const int i = p - s * (s + 1) / 2;
-  const int j = s - i;
-  const int s_lo = tri_root_dev(p0);
-  const int ws = max(0, p0 - s_lo - 1);
-
-  // anti-diagonal / position of the window entries this thread stages
-  int es[NW], ei[NW];
-#pragma unroll
-  for (int r = 0; r < NW; ++r) {
-    const int q = ws + tid + r * TPB;
-    const int sq = tri_root_dev(q);
-    es[r] = sq;
-    ei[r] = q - sq * (sq + 1) / 2;
-  }
-
-  const T *X0 = x + mi.off;
-  const T *X1 = X0 + nn;
-  const T *X2 = X1 + nn;
-  const T *K = kc + mi.off;
-
-  // plane kk of the window: global -> registers (Dirichlet values of x zeroed)
-  Node4<T> pre[NW];
-  auto fetch = [&](int kk) {
-    const int ps = (int)tri(n + 1 - kk);
-    const int64_t base = plane_base(n, kk);
-#pragma unroll
-    for (int r = 0; r < NW; ++r) {
-      const int e = tid + r * TPB;
-      const int q = ws + e;
-      Node4<T> v;
-      v.x0 = v.x1 = v.x2 = v.k = T(0);
-      if (e < wl && q < ps) {
-        const int64_t g = base + q;
-        v.x0 = X0[g];
-        v.x1 = X1[g];
-        v.x2 = X2[g];
-        v.k = K[g];
-        const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
-        if ((mi.dmask >> z) & 1u) v.x0 = v.x1 = v.x2 = T(0);
-      }
-      pre[r] = v;
-    }
-  };
-  // registers -> LDS slot of plane kk
-  auto put = [&](int kk) {
-    Pair<T> *da = bufA + (kk % 3) * wl;
-    Pair<T> *db = bufB + (kk % 3) * wl;
-#pragma unroll
-    for (int r = 0; r < NW; ++r) {
-      const int e = tid + r * TPB;
-      if (e < wl) {
-        da[e] = Pair<T>{pre[r].x0, pre[r].x1};
-        db[e] = Pair<T>{pre[r].x2, pre[r].k};
-      }
-    }
-  };
-
-  fetch(w.ka - 1);
-  put(w.ka - 1);
-  fetch(w.ka);
-  put(w.ka);
-  fetch(w.ka + 1);
-  put(w.ka + 1);
-  __syncthreads();
-  const int e0 = p - ws;
-  const bool col_ok = (s >= 2) && (i >= 1) && (j >= 1);
-
-  for (int kk = w.ka; kk < w.kb; ++kk) {
-    // the plane needed by the next step is loaded while this one computes
-    const bool more = kk + 2 <= w.kb;
-    if (more) fetch(kk + 2);
-    if (col_ok && s + kk <= n - 1) {
-      const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
-      const int o0 = (kk % 3) * wl + e0;
-      const int op = ((kk + 1) % 3) * wl + e0;
-      auto rd = [&](int o) {
-        const Pair<T> a = bufA[o], b = bufB[o];
-        return Node4<T>{a.a, a.b, b.a, b.b};
-      };
-      const Node4<T> c = rd(o0);
-      Node4<T> nb[NDIR];
-#pragma unroll
-      for (int d = 0; d < NDIR; ++d) {
-        const int o = DIR_K[d] > 0 ? op : (DIR_K[d] < 0 ? om : o0);
-        nb[d] = rd(o + dir_a(d) + dir_b(d) * s);
-      }
-      // LDS reads and the scalar loads of the stencil constants share one
-      // wait counter: take all neighbour records before any constant load
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-      __builtin_amdgcn_sched_barrier(0);
-      T y0 = T(0), y1 = T(0), y2 = T(0);
-      if constexpr (METHOD == METHOD_SCALED) {
-        const StencilConst<T> &sc = scs[w.macro];
-#pragma unroll
-        for (int pr = 0; pr < NPAIR; ++pr) {
-          T z0 = T(0), z1 = T(0), z2 = T(0);
-          T a0 = T(0), a1 = T(0), a2 = T(0);
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int d = 2 * pr + h;
-            const int np = DIR_NT[d] == 6 ? 3 : 2;
-            const T dx0 = nb[d].x0 - c.x0, dx1 = nb[d].x1 - c.x1, dx2 = nb[d].x2 - c.x2;
-            T ring = nb[RING_V[d][0]].k + nb[RING_VM[d][0]].k;
-#pragma unroll
-            for (int q = 1; q < np; ++q) ring += nb[RING_V[d][q]].k + nb[RING_VM[d][q]].k;
-            const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
-            const T kh = fma(sc.w_end, c.k + nb[d].k, wr * ring);
-            z0 = fma(kh, dx0, z0);
-            z1 = fma(kh, dx1, z1);
-            z2 = fma(kh, dx2, z2);
-            if constexpr (A0) {
-              a0 += dx0;
-              a1 += dx1;
-              a2 += dx2;
-            }
-            if constexpr (CORR) {
-              T w0 = T(0), w1 = T(0), w2 = T(0);
-#pragma unroll
-              for (int q = 0; q < np; ++q) {
-                const T dk = nb[RING_V[d][q]].k - nb[RING_VM[d][q]].k;
-                w0 = fma(dk, sc.cax[d][q][0], w0);
-                w1 = fma(dk, sc.cax[d][q][1], w1);
-                w2 = fma(dk, sc.cax[d][q][2], w2);
-              }
-              cross_acc(w0, w1, w2, dx0, dx1, dx2, y0, y1, y2);
-            }
-          }
-          sym_mv_acc(sc.shat[pr], z0, z1, z2, y0, y1, y2);
-          if constexpr (A0) sym_mv_acc(sc.a0[pr], a0, a1, a2, y0, y1, y2);
-        }
-      } else {
-        const ElemConst<T> &ec = ecs[w.macro];
-#pragma unroll
-        for (int t = 0; t < NTET; ++t) {
-          const int v1 = TET_V[t][0], v2 = TET_V[t][1], v3 = TET_V[t][2];
-          const T kb = T(0.25) * (c.k + nb[v1].k + nb[v2].k + nb[v3].k);
-          T u0 = T(0), u1 = T(0), u2 = T(0);
-          T q0 = T(0), q1 = T(0), q2 = T(0);
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc) {
-            const int v = TET_V[t][cc];
-            const T d0 = nb[v].x0 - c.x0, d1 = nb[v].x1 - c.x1, d2 = nb[v].x2 - c.x2;
-            const T *B = ec.b1[t][cc + 1];
-            u0 = fma(B[0], d0, fma(B[1], d1, fma(B[2], d2, u0)));
-            u1 = fma(B[3], d0, fma(B[4], d1, fma(B[5], d2, u1)));
-            u2 = fma(B[6], d0, fma(B[7], d1, fma(B[8], d2, u2)));
-            if constexpr (A0) {
-              const T *C = ec.b0[t][cc + 1];
-              q0 = fma(C[0], d0, fma(C[1], d1, fma(C[2], d2, q0)));
-              q1 = fma(C[3], d0, fma(C[4], d1, fma(C[5], d2, q1)));
-              q2 = fma(C[6], d0, fma(C[7], d1, fma(C[8], d2, q2)));
-            }
-          }
-          y0 = fma(kb, u0, y0 + q0);
-          y1 = fma(kb, u1, y1 + q1);
-          y2 = fma(kb, u2, y2 + q2);
-        }
-      }
-      const int64_t g = mi.off + plane_base(n, kk) + p;
-      if constexpr (RESID) {
-        y0 = f[g] - y0;
-        y1 = f[g + nn] - y1;
-        y2 = f[g + 2 * nn] - y2;
-      }
-      y[g] = y0;
-      y[g + nn] = y1;
-      y[g + 2 * nn] = y2;
-    }
-    __syncthreads();
-    if (more) put(kk + 2);               // overwrites the slot of plane kk-1
-    __syncthreads();
-  }
-}
 
 // Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
 // computes the partial row of its macro; copies are summed afterwards.
@@ -400,59 +150,6 @@ __global__ __launch_bounds__(256) void k_finish(const int64_t *__restrict__ ptr,
 // ------------------------------------------------------------ launchers
 namespace {
 
-template <typename T>
-const StencilConst<T> *sc_ptr(hhg_ctx *h);
-template <>
-const StencilConst<double> *sc_ptr<double>(hhg_ctx *h) { return h->d_sc64; }
-template <>
-const StencilConst<float> *sc_ptr<float>(hhg_ctx *h) { return h->d_sc32; }
-template <typename T>
-const ElemConst<T> *ec_ptr(hhg_ctx *h);
-template <>
-const ElemConst<double> *ec_ptr<double>(hhg_ctx *h) { return h->d_ec64; }
-template <>
-const ElemConst<float> *ec_ptr<float>(hhg_ctx *h) { return h->d_ec32; }
-
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
-int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
-  const int wl = h->wl_max;
-  const size_t lds = 6 * (size_t)wl * sizeof(Pair<T>);
-  auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB>;
-  if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
-  hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
-                     ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
-  HHG_HIP(hipGetLastError());
-  return HHG_OK;
-}
-
-// Positions per work item (= threads): 256 or 512; window entries per
-// thread: up to 2 (levels <= 7 with 256, <= 8 with 512) or up to 6.
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
-int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
-  if (h->n_work == 0) return HHG_OK;
-  const int nw = (h->wl_max + h->chunk - 1) / h->chunk;
-  if (h->chunk == 256) {
-    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256>(h, x, k, f, y, st);
-    if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256>(h, x, k, f, y, st);
-  } else if (h->chunk == 512) {
-    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 512>(h, x, k, f, y, st);
-    if (nw <= 3) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 3, 512>(h, x, k, f, y, st);
-  }
-  return fail(HHG_EINVAL, "interior window larger than supported");
-}
-
-template <typename T, int METHOD, bool RESID>
-int launch_interior_v(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
-  const bool corr = METHOD == METHOD_SCALED && h->op.corr == HHG_CORR_PHYSICAL;
-  const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
-  if (corr && a0) return launch_interior<T, METHOD, RESID, true, true>(h, x, k, f, y, st);
-  if (corr) return launch_interior<T, METHOD, RESID, true, false>(h, x, k, f, y, st);
-  if (a0) return launch_interior<T, METHOD, RESID, false, true>(h, x, k, f, y, st);
-  return launch_interior<T, METHOD, RESID, false, false>(h, x, k, f, y, st);
-}
-
 template <typename T, bool RESID>
 int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, T *y,
                     hipStream_t st) {
@@ -529,6 +226,19 @@ int apply_entry(hhg_ctx *h, int prec, int method, const void *f, const void *x, 
   int rc = ensure_device(h);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  if (prec == HHG_F64)
+    return apply_t<double>(h, method, (const double *)f, (const double *)x, (const double *)k,
+                           (double *)y, st);
+  return apply_t<float>(h, method, (const float *)f, (const float *)x, (const float *)k,
+                        (float *)y, st);
+}
+
+// Operator application for the solvers: no argument checks beyond the
+// device upload (the caller owns consistent, aligned, non-overlapping data).
+int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
+                   void *y, hipStream_t st) {
+  int rc = ensure_device(h);
+  if (rc) return rc;
   if (prec == HHG_F64)
     return apply_t<double>(h, method, (const double *)f, (const double *)x, (const double *)k,
                            (double *)y, st);

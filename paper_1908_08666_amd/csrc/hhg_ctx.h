@@ -48,6 +48,8 @@ struct hhg_ctx {
   int64_t n_grp = 0;
   uint8_t *d_flags = nullptr;
   hipStream_t side = nullptr;                // macro-boundary rows run here
+  hipStream_t solve_stream = nullptr;        // solvers run (and capture graphs) here
+  void *h_state = nullptr;                   // pinned host mirror of the solver state
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // kernel timing (hhg_profile_*)

@@ -346,6 +346,8 @@ void free_ctx(hhg_ctx *h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->solve_stream) (void)hipStreamDestroy(h->solve_stream);
+  if (h->h_state) (void)hipHostFree(h->h_state);
   delete h;
 }
 
@@ -638,6 +640,7 @@ int ensure_device(hhg_ctx *h) {
   if ((rc = upload(&h->d_grp_slot, h->grp_slot.data(), h->grp_slot.size()))) return rc;
   if ((rc = upload(&h->d_flags, h->flags.data(), h->flags.size()))) return rc;
   HHG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  HHG_HIP(hipStreamCreateWithFlags(&h->solve_stream, hipStreamNonBlocking));
   HHG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
   HHG_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
   h->on_device = true;

@@ -128,6 +128,46 @@ class Mesh:
         L.check(self._lib.hhg_residual(self._h, prec, m, pf, px, pk, pr, _stream_ptr(stream)))
         return r
 
+    # ------------------------------------------------------------ solvers
+    def solve_opts(self, solver="cg64", precond="block_jacobi", method="scaled", rtol=1e-8,
+                   maxit=20000, inner_rtol=1e-3, check_every=8):
+        return L.SolveOpts({"cg64": L.HHG_CG_F64, "ir32": L.HHG_IR_F32}[solver],
+                           {"none": L.HHG_PRECOND_NONE, "block_jacobi": L.HHG_PRECOND_BLOCK_JACOBI}[precond],
+                           {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method],
+                           int(maxit), float(rtol), float(inner_rtol), int(check_every), 0)
+
+    def workspace_bytes(self, **opts) -> int:
+        o = self.solve_opts(**opts)
+        n = ctypes.c_size_t()
+        L.check(self._lib.hhg_workspace_bytes(self._h, ctypes.byref(o), ctypes.byref(n)))
+        return int(n.value)
+
+    def solve(self, b, k, x=None, workspace=None, stream=None, raise_on_status=True, **opts):
+        """Solve A x = b (``hhg_cg_solve``); returns (x, info dict).  b, k, x
+        are float64 device tensors; x (start vector) defaults to zero."""
+        import torch
+        N = self.n_nodes
+        if x is None:
+            x = torch.zeros((3, N), dtype=torch.float64, device=b.device)
+        o = self.solve_opts(**opts)
+        nbytes = ctypes.c_size_t()
+        L.check(self._lib.hhg_workspace_bytes(self._h, ctypes.byref(o), ctypes.byref(nbytes)))
+        if workspace is None or workspace.numel() < nbytes.value:
+            workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=b.device)
+        base = workspace.data_ptr()
+        ws = ctypes.c_void_p(base + ((-base) % 256))
+        info = L.SolveInfo()
+        rc = self._lib.hhg_cg_solve(self._h, ctypes.byref(o), _dev_ptr(b, (3, N), torch.float64),
+                                    _dev_ptr(k, (N,), torch.float64), _dev_ptr(x, (3, N), torch.float64),
+                                    ws, ctypes.byref(info), _stream_ptr(stream))
+        out = dict(iterations=info.iterations, outer_iterations=info.outer_iterations,
+                   status=L.STATUS_NAMES.get(info.status if rc == L.HHG_OK or info.status else rc, rc),
+                   code=rc, rel_residual=info.rel_residual, seconds=info.seconds,
+                   message=(self._lib.hhg_last_error() or b"").decode())
+        if rc not in (L.HHG_OK,) and raise_on_status:
+            L.check(rc)
+        return x, out
+
     # ------------------------------------------------------------ tracing
     def profile_enable(self, on=True):
         L.check(self._lib.hhg_profile_enable(self._h, 1 if on else 0))
