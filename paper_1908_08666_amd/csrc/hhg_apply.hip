@@ -188,6 +188,16 @@ int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, 
 // before the call's work is complete on the caller's stream.
 template <typename T>
 int apply_t(hhg_ctx *h, int method, const T *f, const T *x, const T *k, T *y, hipStream_t st) {
+  if (h->serial_apply) {                    // one stream: clean per-kernel timings
+    int rc = method == METHOD_SCALED
+                 ? (f ? launch_interior_v<T, METHOD_SCALED, true>(h, x, k, f, y, st)
+                      : launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, st))
+                 : (f ? launch_interior_v<T, METHOD_ONTHEFLY, true>(h, x, k, f, y, st)
+                      : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, st));
+    if (rc) return rc;
+    return f ? launch_boundary<T, true>(h, method, x, k, f, y, st)
+             : launch_boundary<T, false>(h, method, x, k, f, y, st);
+  }
   HHG_HIP(hipEventRecord(h->ev_fork, st));
   HHG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
   int rc;

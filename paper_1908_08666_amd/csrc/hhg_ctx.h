@@ -29,6 +29,8 @@ struct hhg_ctx {
   int wl_max = 0;                            // LDS window entries per plane
   int planes_per_item = 4;
   int chunk = 256;                           // positions per interior work item
+  bool stage_dma = false;                    // interior staging by LDS-DMA loads (opt-in)
+  bool serial_apply = false;                 // boundary rows on the caller's stream too
   bool on_device = false;                    // tables uploaded (first device call)
   int device = -1;
 

@@ -23,6 +23,83 @@
 
 namespace hhg {
 
+// Row i of the operator applied to x for a macro-interior node from its
+// 15-point neighbourhood: physical scaling (METHOD_SCALED) or nodal
+// integration over the 24 elements (METHOD_ONTHEFLY).
+template <typename T, int METHOD, bool CORR, bool A0>
+__device__ __forceinline__ void node_rows(const Node4<T> &c, const Node4<T> (&nb)[NDIR],
+                                          const StencilConst<T> &sc, const ElemConst<T> &ec,
+                                          T &y0, T &y1, T &y2) {
+  y0 = T(0);
+  y1 = T(0);
+  y2 = T(0);
+  if constexpr (METHOD == METHOD_SCALED) {
+#pragma unroll
+    for (int pr = 0; pr < NPAIR; ++pr) {
+      T z0 = T(0), z1 = T(0), z2 = T(0);
+      T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int d = 2 * pr + h;
+        const int np = DIR_NT[d] == 6 ? 3 : 2;
+        const T dx0 = nb[d].x0 - c.x0, dx1 = nb[d].x1 - c.x1, dx2 = nb[d].x2 - c.x2;
+        T ring = nb[RING_V[d][0]].k + nb[RING_VM[d][0]].k;
+#pragma unroll
+        for (int q = 1; q < np; ++q) ring += nb[RING_V[d][q]].k + nb[RING_VM[d][q]].k;
+        const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
+        const T kh = fma(sc.w_end, c.k + nb[d].k, wr * ring);
+        z0 = fma(kh, dx0, z0);
+        z1 = fma(kh, dx1, z1);
+        z2 = fma(kh, dx2, z2);
+        if constexpr (A0) {
+          a0 += dx0;
+          a1 += dx1;
+          a2 += dx2;
+        }
+        if constexpr (CORR) {
+          T w0 = T(0), w1 = T(0), w2 = T(0);
+#pragma unroll
+          for (int q = 0; q < np; ++q) {
+            const T dk = nb[RING_V[d][q]].k - nb[RING_VM[d][q]].k;
+            w0 = fma(dk, sc.cax[d][q][0], w0);
+            w1 = fma(dk, sc.cax[d][q][1], w1);
+            w2 = fma(dk, sc.cax[d][q][2], w2);
+          }
+          cross_acc(w0, w1, w2, dx0, dx1, dx2, y0, y1, y2);
+        }
+      }
+      sym_mv_acc(sc.shat[pr], z0, z1, z2, y0, y1, y2);
+      if constexpr (A0) sym_mv_acc(sc.a0[pr], a0, a1, a2, y0, y1, y2);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < NTET; ++t) {
+      const int v1 = TET_V[t][0], v2 = TET_V[t][1], v3 = TET_V[t][2];
+      const T kb = T(0.25) * (c.k + nb[v1].k + nb[v2].k + nb[v3].k);
+      T u0 = T(0), u1 = T(0), u2 = T(0);
+      T q0 = T(0), q1 = T(0), q2 = T(0);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const int v = TET_V[t][cc];
+        const T d0 = nb[v].x0 - c.x0, d1 = nb[v].x1 - c.x1, d2 = nb[v].x2 - c.x2;
+        const T *B = ec.b1[t][cc + 1];
+        u0 = fma(B[0], d0, fma(B[1], d1, fma(B[2], d2, u0)));
+        u1 = fma(B[3], d0, fma(B[4], d1, fma(B[5], d2, u1)));
+        u2 = fma(B[6], d0, fma(B[7], d1, fma(B[8], d2, u2)));
+        if constexpr (A0) {
+          const T *C = ec.b0[t][cc + 1];
+          q0 = fma(C[0], d0, fma(C[1], d1, fma(C[2], d2, q0)));
+          q1 = fma(C[3], d0, fma(C[4], d1, fma(C[5], d2, q1)));
+          q2 = fma(C[6], d0, fma(C[7], d1, fma(C[8], d2, q2)));
+        }
+      }
+      y0 = fma(kb, u0, y0 + q0);
+      y1 = fma(kb, u1, y1 + q1);
+      y2 = fma(kb, u2, y2 + q2);
+    }
+  }
+}
+
 template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
 __global__ __launch_bounds__(TPB) void k_interior(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
@@ -132,74 +209,8 @@ __global__ __launch_bounds__(TPB) void k_interior(
       __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
       __builtin_amdgcn_sched_barrier(0);
-      T y0 = T(0), y1 = T(0), y2 = T(0);
-      if constexpr (METHOD == METHOD_SCALED) {
-        const StencilConst<T> &sc = scs[w.macro];
-#pragma unroll
-        for (int pr = 0; pr < NPAIR; ++pr) {
-          T z0 = T(0), z1 = T(0), z2 = T(0);
-          T a0 = T(0), a1 = T(0), a2 = T(0);
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int d = 2 * pr + h;
-            const int np = DIR_NT[d] == 6 ? 3 : 2;
-            const T dx0 = nb[d].x0 - c.x0, dx1 = nb[d].x1 - c.x1, dx2 = nb[d].x2 - c.x2;
-            T ring = nb[RING_V[d][0]].k + nb[RING_VM[d][0]].k;
-#pragma unroll
-            for (int q = 1; q < np; ++q) ring += nb[RING_V[d][q]].k + nb[RING_VM[d][q]].k;
-            const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
-            const T kh = fma(sc.w_end, c.k + nb[d].k, wr * ring);
-            z0 = fma(kh, dx0, z0);
-            z1 = fma(kh, dx1, z1);
-            z2 = fma(kh, dx2, z2);
-            if constexpr (A0) {
-              a0 += dx0;
-              a1 += dx1;
-              a2 += dx2;
-            }
-            if constexpr (CORR) {
-              T w0 = T(0), w1 = T(0), w2 = T(0);
-#pragma unroll
-              for (int q = 0; q < np; ++q) {
-                const T dk = nb[RING_V[d][q]].k - nb[RING_VM[d][q]].k;
-                w0 = fma(dk, sc.cax[d][q][0], w0);
-                w1 = fma(dk, sc.cax[d][q][1], w1);
-                w2 = fma(dk, sc.cax[d][q][2], w2);
-              }
-              cross_acc(w0, w1, w2, dx0, dx1, dx2, y0, y1, y2);
-            }
-          }
-          sym_mv_acc(sc.shat[pr], z0, z1, z2, y0, y1, y2);
-          if constexpr (A0) sym_mv_acc(sc.a0[pr], a0, a1, a2, y0, y1, y2);
-        }
-      } else {
-        const ElemConst<T> &ec = ecs[w.macro];
-#pragma unroll
-        for (int t = 0; t < NTET; ++t) {
-          const int v1 = TET_V[t][0], v2 = TET_V[t][1], v3 = TET_V[t][2];
-          const T kb = T(0.25) * (c.k + nb[v1].k + nb[v2].k + nb[v3].k);
-          T u0 = T(0), u1 = T(0), u2 = T(0);
-          T q0 = T(0), q1 = T(0), q2 = T(0);
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc) {
-            const int v = TET_V[t][cc];
-            const T d0 = nb[v].x0 - c.x0, d1 = nb[v].x1 - c.x1, d2 = nb[v].x2 - c.x2;
-            const T *B = ec.b1[t][cc + 1];
-            u0 = fma(B[0], d0, fma(B[1], d1, fma(B[2], d2, u0)));
-            u1 = fma(B[3], d0, fma(B[4], d1, fma(B[5], d2, u1)));
-            u2 = fma(B[6], d0, fma(B[7], d1, fma(B[8], d2, u2)));
-            if constexpr (A0) {
-              const T *C = ec.b0[t][cc + 1];
-              q0 = fma(C[0], d0, fma(C[1], d1, fma(C[2], d2, q0)));
-              q1 = fma(C[3], d0, fma(C[4], d1, fma(C[5], d2, q1)));
-              q2 = fma(C[6], d0, fma(C[7], d1, fma(C[8], d2, q2)));
-            }
-          }
-          y0 = fma(kb, u0, y0 + q0);
-          y1 = fma(kb, u1, y1 + q1);
-          y2 = fma(kb, u2, y2 + q2);
-        }
-      }
+      T y0, y1, y2;
+      node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
       const int64_t g = mi.off + plane_base(n, kk) + p;
       if constexpr (RESID) {
         y0 = f[g] - y0;
@@ -217,6 +228,150 @@ __global__ __launch_bounds__(TPB) void k_interior(
 }
 
 
+// Same rows with the plane windows copied straight into LDS by the loader
+// (global_load_lds, 4 bytes per lane), so staging costs no registers and no
+// LDS write instructions.  Plane kk lives in slot kk % NSLOT as four arrays
+// (x0, x1, x2, k) of `wl` entries; plane kk+2 is loaded while plane kk is
+// computed, and one barrier per plane suffices: the slot being filled was
+// last read two planes earlier.  Every lane zeroes the Dirichlet values of x
+// among the entries it loaded itself, after its own loads have landed.
+constexpr int NSLOT = 4;
+
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int ROUNDS, int TPB>
+__global__ __launch_bounds__(TPB) void k_interior_dma(
+    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
+    const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
+    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
+    T *__restrict__ y, int64_t nn, int wl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);              // [NSLOT][4][wl]
+
+  const WorkItem w = work[blockIdx.x];
+  if (w.macro < 0) return;                  // padding item of the XCD-aware order
+  const MacroInfo mi = minfo[w.macro];
+  const int n = mi.n;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int p0 = w.chunk * TPB;
+  const int p = p0 + tid;
+  const int s = tri_root_dev(p);
+  const int i = p - s * (s + 1) / 2;
+  const int j = s - i;
+  const int s_lo = tri_root_dev(p0);
+  const int ws = max(0, p0 - s_lo - 1);
+
+  const T *src[4] = {x + mi.off, x + nn + mi.off, x + 2 * nn + mi.off, kc + mi.off};
+  // byte offset (inside one window array) of this lane's 4-byte piece per
+  // round, and the window entry it starts (for the Dirichlet fix-up)
+  constexpr int RB = TPB * 4;                               // bytes per round
+  int es[ROUNDS], ei[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int q = ws + (r * RB + wave * 256 + lane * 4) / (int)sizeof(T);
+    const int sq = tri_root_dev(q);
+    es[r] = sq;
+    ei[r] = q - sq * (sq + 1) / 2;
+  }
+
+  auto issue = [&](int kk) {
+    const int ps = (int)tri(n + 1 - kk);
+    const int64_t base = plane_base(n, kk) + ws;
+    const int nbytes = max(0, min(wl, ps - ws)) * (int)sizeof(T);
+    T *slot = lds + (kk % NSLOT) * 4 * wl;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int wb = r * RB + wave * 256;                   // wave-uniform
+      if (wb + lane * 4 < nbytes) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          __builtin_amdgcn_global_load_lds(
+              reinterpret_cast<const char *>(src[a] + base) + wb + lane * 4,
+              (__attribute__((address_space(3))) void *)(reinterpret_cast<char *>(slot + a * wl) + wb),
+              4, 0, 0);
+      }
+    }
+  };
+  auto fix = [&](int kk) {                  // after this wave's loads landed
+    const int ps = (int)tri(n + 1 - kk);
+    T *slot = lds + (kk % NSLOT) * 4 * wl;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int off = r * RB + wave * 256 + lane * 4;
+      if (off % (int)sizeof(T) != 0) continue;
+      const int e = off / (int)sizeof(T);
+      if (e >= wl || ws + e >= ps) continue;
+      const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
+      if ((mi.dmask >> z) & 1u) {
+        slot[e] = T(0);
+        slot[wl + e] = T(0);
+        slot[2 * wl + e] = T(0);
+      }
+    }
+  };
+  auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
+
+  issue(w.ka - 1);
+  issue(w.ka);
+  issue(w.ka + 1);
+  wait_loads();
+  fix(w.ka - 1);
+  fix(w.ka);
+  fix(w.ka + 1);
+  __syncthreads();
+  const int e0 = p - ws;
+  const bool col_ok = (s >= 2) && (i >= 1) && (j >= 1);
+
+  for (int kk = w.ka; kk < w.kb; ++kk) {
+    const bool more = kk + 2 <= w.kb;
+    if (more) issue(kk + 2);
+    if (col_ok && s + kk <= n - 1) {
+      const T *Lm = lds + ((kk + NSLOT - 1) % NSLOT) * 4 * wl + e0;   // plane kk-1
+      const T *L0 = lds + (kk % NSLOT) * 4 * wl + e0;
+      const T *Lp = lds + ((kk + 1) % NSLOT) * 4 * wl + e0;
+      auto rd = [&](const T *L, int o) { return Node4<T>{L[o], L[wl + o], L[2 * wl + o], L[3 * wl + o]}; };
+      const Node4<T> c = rd(L0, 0);
+      Node4<T> nb[NDIR];
+#pragma unroll
+      for (int d = 0; d < NDIR; ++d)
+        nb[d] = rd(DIR_K[d] > 0 ? Lp : (DIR_K[d] < 0 ? Lm : L0), dir_a(d) + dir_b(d) * s);
+      // LDS reads and the scalar loads of the stencil constants share one
+      // wait counter: take all neighbour values before any constant load
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+      __builtin_amdgcn_sched_barrier(0);
+      T y0, y1, y2;
+      node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
+      const int64_t g = mi.off + plane_base(n, kk) + p;
+      if constexpr (RESID) {
+        y0 = f[g] - y0;
+        y1 = f[g + nn] - y1;
+        y2 = f[g + 2 * nn] - y2;
+      }
+      y[g] = y0;
+      y[g + nn] = y1;
+      y[g + 2 * nn] = y2;
+    }
+    wait_loads();
+    if (more) fix(kk + 2);
+    __syncthreads();
+  }
+}
+
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int ROUNDS>
+int launch_interior_dma(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
+  constexpr int TPB = 256;
+  const int wl = ROUNDS * TPB * 4 / (int)sizeof(T);        // window entries per array
+  const size_t lds = (size_t)NSLOT * 4 * wl * sizeof(T);
+  auto kern = k_interior_dma<T, METHOD, RESID, CORR, A0, ROUNDS, TPB>;
+  if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
+  hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
+                     ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
+  HHG_HIP(hipGetLastError());
+  return HHG_OK;
+}
+
 template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
 int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
   const int wl = h->wl_max;
@@ -231,18 +386,22 @@ int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hip
   return HHG_OK;
 }
 
-// Positions per work item (= threads): 256 or 512; window entries per
-// thread: up to 2 (levels <= 7 with 256, <= 8 with 512) or up to 6.
+// Positions per work item (= threads): 256; window entries per thread in the
+// register-staged fallback: up to 2 (levels <= 7) or up to 6 (levels 8, 9).
 template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
 int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
   if (h->n_work == 0) return HHG_OK;
+  // LDS-DMA staging while its window ring fits 80 KB (two workgroups per CU)
+  if (h->chunk == 256 && h->stage_dma) {
+    const int rounds = (h->wl_max * (int)sizeof(T) + 1023) / 1024;
+    if (rounds <= 2) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 2>(h, x, k, f, y, st);
+    if (rounds <= 4) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 4>(h, x, k, f, y, st);
+    if (rounds <= 5) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 5>(h, x, k, f, y, st);
+  }
   const int nw = (h->wl_max + h->chunk - 1) / h->chunk;
   if (h->chunk == 256) {
     if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256>(h, x, k, f, y, st);
     if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256>(h, x, k, f, y, st);
-  } else if (h->chunk == 512) {
-    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 512>(h, x, k, f, y, st);
-    if (nw <= 3) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 3, 512>(h, x, k, f, y, st);
   }
   return fail(HHG_EINVAL, "interior window larger than supported");
 }

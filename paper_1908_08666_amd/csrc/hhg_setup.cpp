@@ -561,10 +561,11 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   // --------------------------------------------------- interior work list
   const char *env = std::getenv("HHG_PLANES_PER_ITEM");
   if (env) h->planes_per_item = std::max(1, std::atoi(env));
-  const char *envc = std::getenv("HHG_CHUNK");
-  h->chunk = (envc && std::atoi(envc) == 512) ? 512 : 256;
-  // a 512-position window beyond level 8 needs more than 3 entries per thread
-  if (h->max_level > 8) h->chunk = 256;
+  const char *envs = std::getenv("HHG_SERIAL_APPLY");
+  h->serial_apply = envs && std::atoi(envs) == 1;
+  const char *envd = std::getenv("HHG_STAGE_DMA");
+  h->stage_dma = envd && std::atoi(envd) == 1;
+  h->chunk = 256;
   const int CH = h->chunk;
   std::vector<WorkItem> natural;
   int wl_max = 0;
