@@ -68,6 +68,57 @@ def cpu_baseline(level, rows_sample, seed=0):
                        f"single-threaded NumPy")
 
 
+def carreau_workload(level, dev, solve=True, maxit=60000):
+    """Generalized-Newtonian eps-operator on the 24-macro cube: Carreau
+    viscosity of a seeded smooth velocity field (scaled for a viscosity
+    contrast of about 1e2), then FP64 CG vs FP32 + FP64 refinement to 1e-8."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1908_08666_amd import Mesh
+    law = dict(W.CARREAU_DEFAULT)
+    mesh = Mesh(W.cube24(), level, mu1=1.0)
+    xyz = mesh.coords().T
+    # amplitude: max |eps| of the analytic field ~ 1e4 gives eta ~ 1e-2 there
+    Gx = W.velocity_gradient(xyz, W.rng_for(3, 0), 1.0)
+    E = 0.5 * (Gx + np.swapaxes(Gx, 1, 2))
+    scale = 1e4 / np.sqrt(np.einsum("ncd,ncd->n", E, E).max())
+    u = torch.from_numpy(np.ascontiguousarray(W.velocity_field(xyz, W.rng_for(3, 0), scale).T)).to(dev)
+    ws = None
+    k = mesh.nodal_viscosity(u, **law)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        k = mesh.nodal_viscosity(u, k=k, **law)
+    torch.cuda.synchronize()
+    t_visc = (time.perf_counter() - t0) / reps
+    out = dict(level=level, macros=mesh.n_macro, unknown_dofs=3 * mesh.n_unknown,
+               viscosity_ms=round(t_visc * 1e3, 3),
+               viscosity_min=float(k.min()), viscosity_max=float(k.max()),
+               contrast=float(k.max() / k.min()))
+    if solve:
+        b = torch.from_numpy(consistent_random(mesh, W.rng_for(3, 99), 3)).to(dev, torch.float64)
+        fl = torch.from_numpy(mesh.flags()).to(dev)
+        b[:, (fl & 1) > 0] = 0.0
+        for name, opts in (("cg64", dict(solver="cg64")), ("ir32", dict(solver="ir32", inner_rtol=1e-2))):
+            nb = mesh.workspace_bytes(**opts)
+            if ws is None or ws.numel() < nb + 256:
+                ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+            for rep in range(2):
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = mesh.solve(b, k, x=x, workspace=ws, rtol=1e-8, check_every=16,
+                                     maxit=maxit, raise_on_status=False, **opts)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+            out[name] = dict(iterations=info["iterations"], outer=info["outer_iterations"],
+                             seconds=round(wall, 4), rel_residual=info["rel_residual"],
+                             status=info["status"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +129,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--solve", action="store_true", help="also time CG / IR solves to 1e-8")
+    ap.add_argument("--carreau-level", type=int, default=7)
+    ap.add_argument("--carreau", action="store_true",
+                    help="also run the 24-macro Carreau eps-operator workload (viscosity + solves)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
@@ -200,6 +254,11 @@ def main():
                                 seconds=round(wall, 4), rel_residual=info["rel_residual"],
                                 status=info["status"])
         extra["solve_to_1e-8"] = solves
+
+    if args.carreau:
+        sets64 = sets32 = None
+        torch.cuda.empty_cache()
+        extra["carreau_cube24"] = carreau_workload(args.carreau_level, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -206,6 +206,27 @@ int hhg_workspace_bytes(hhg_handle h, const hhg_solve_opts *o, size_t *bytes);
 int hhg_cg_solve(hhg_handle h, const hhg_solve_opts *o, const double *b, const double *k,
                  double *x, void *workspace, hhg_solve_info *info, void *stream);
 
+/* Generalized-Newtonian viscosity at the nodes from a velocity field
+ * (Sec. 3: the strain rate |D(u)|^2 is evaluated from a local least-squares
+ * fit of u; Carreau law eq. carreau of Sec. 5.2.2):
+ *     mu_i = eta_inf + (eta0 - eta_inf) (1 + kappa |eps(u)_i|^2)^r,
+ * |eps|^2 = eps : eps.  Macro-interior nodes: gradient of the affine
+ * least-squares fit over the 15-node patch (exact for quadratic u there).
+ * Nodes on macro boundaries: volume-weighted mean of the gradients of all
+ * elements at the node (the patch of the paper's quadratic fit on the lower
+ * dimensional primitives is not specified).  u: FP64 [3][n] consistent device
+ * vector, every node (Dirichlet ones included) used as given; k: FP64 [n]
+ * device output, consistent.  workspace: hhg_viscosity_workspace_bytes bytes
+ * of device memory.  Errors: HHG_EINVAL for null/misaligned pointers or
+ * parameters outside eta0 >= eta_inf > 0, kappa >= 0.  Asynchronous.        */
+typedef struct {
+  double eta0, eta_inf, kappa, r;
+} hhg_carreau;
+
+int hhg_viscosity_workspace_bytes(hhg_handle h, size_t *bytes);
+int hhg_nodal_viscosity(hhg_handle h, const double *u, const hhg_carreau *law, double *k,
+                        void *workspace, void *stream);
+
 /* Kernel timing (tracing aid, not needed for results).  While enabled,
  * every kernel the library launches is bracketed by a pair of HIP events on
  * the launch stream.  hhg_profile_read synchronizes those events and returns,

@@ -51,6 +51,11 @@ HHG_CG_F64, HHG_IR_F32 = 0, 1
 HHG_PRECOND_NONE, HHG_PRECOND_BLOCK_JACOBI = 0, 1
 
 
+class Carreau(ctypes.Structure):
+    _fields_ = [("eta0", ctypes.c_double), ("eta_inf", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("r", ctypes.c_double)]
+
+
 class HHGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -75,6 +80,8 @@ SIGNATURES = {
     "hhg_workspace_bytes": ([_VP, ctypes.POINTER(SolveOpts), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hhg_cg_solve": ([_VP, ctypes.POINTER(SolveOpts), _VP, _VP, _VP, _VP, ctypes.POINTER(SolveInfo), _VP],
                      ctypes.c_int),
+    "hhg_viscosity_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hhg_nodal_viscosity": ([_VP, _VP, ctypes.POINTER(Carreau), _VP, _VP, _VP], ctypes.c_int),
     "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hhg_last_error": ([], ctypes.c_char_p),

@@ -21,11 +21,13 @@ struct hhg_ctx {
                                              // bit3 node has copies in other macros
   std::vector<hhg::StencilConst<double>> sc64;
   std::vector<hhg::ElemConst<double>> ec64;
+  std::vector<hhg::StrainConst> stc;
   std::vector<hhg::WorkItem> work;
   std::vector<int32_t> bijk;                 // non-Dirichlet boundary slots, packed (i,j,k)
   std::vector<int32_t> bblk;                 // macro of each boundary-row block
   std::vector<int64_t> dslot;                // Dirichlet slots (rows written as zero)
-  std::vector<int64_t> grp_ptr, grp_slot;
+  std::vector<int64_t> grp_ptr, grp_slot;    // non-Dirichlet copy groups
+  std::vector<int64_t> agrp_ptr, agrp_slot;  // all copy groups
   int wl_max = 0;                            // LDS window entries per plane
   int planes_per_item = 4;
   int chunk = 256;                           // positions per interior work item
@@ -48,6 +50,10 @@ struct hhg_ctx {
   int64_t *d_grp_ptr = nullptr;              // interface copy groups (>= 2 copies)
   int64_t *d_grp_slot = nullptr;
   int64_t n_grp = 0;
+  int64_t *d_agrp_ptr = nullptr;             // all copy groups (Dirichlet ones too)
+  int64_t *d_agrp_slot = nullptr;
+  int64_t n_agrp = 0;
+  hhg::StrainConst *d_stc = nullptr;
   uint8_t *d_flags = nullptr;
   hipStream_t side = nullptr;                // macro-boundary rows run here
   hipStream_t solve_stream = nullptr;        // solvers run (and capture graphs) here

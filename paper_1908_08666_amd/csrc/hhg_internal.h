@@ -95,6 +95,16 @@ struct ElemConst {
   T b0[NTET][4][9];     // constant form
 };
 
+// Constants of the nodal strain-rate estimate for one macro: least-squares
+// weights of the 14 neighbour differences (affine fit on the 15-node patch)
+// and the P1 gradients of the 24 elements around a node (vertex 0 = node,
+// 1..3 = TET_V), all micro elements having the same volume.
+struct StrainConst {
+  double w[NDIR][3];
+  double grad[NTET][4][3];
+  double vol;
+};
+
 // Interior work item: macro, chunk of plane positions, plane range [ka, kb).
 struct WorkItem {
   int32_t macro, chunk, ka, kb;

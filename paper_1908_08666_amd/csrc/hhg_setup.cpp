@@ -156,7 +156,37 @@ bool verify_lattice_tables(std::string &why) {
 struct MacroTables {
   StencilConst<double> sc;
   ElemConst<double> ec;
+  StrainConst st;
 };
+
+// Least-squares weights of the affine fit on the 15-node patch: with
+// d = x_{i+d} - x_i and M = sum_d d d^T, grad u = sum_d M^{-1} d (u_{i+d} - u_i)
+// (the neighbour offsets are symmetric, so the constant decouples).
+int build_strain_tables(const Vec3 e[3], StrainConst &st) {
+  Mat3 M{};
+  Vec3 dv[NDIR];
+  for (int d = 0; d < NDIR; ++d) {
+    for (int c = 0; c < 3; ++c) dv[d][c] = DIR_I[d] * e[0][c] + DIR_J[d] * e[1][c] + DIR_K[d] * e[2][c];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) M[a][b] += dv[d][a] * dv[d][b];
+  }
+  const double det = det3(M);
+  if (!(std::fabs(det) > 0.0)) return fail(HHG_EINVAL, "singular least-squares patch");
+  Mat3 Mi;
+  Mi[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) / det;
+  Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / det;
+  Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
+  Mi[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / det;
+  Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+  Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+  Mi[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / det;
+  Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+  Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+  for (int d = 0; d < NDIR; ++d)
+    for (int a = 0; a < 3; ++a)
+      st.w[d][a] = Mi[a][0] * dv[d][0] + Mi[a][1] * dv[d][1] + Mi[a][2] * dv[d][2];
+  return HHG_OK;
+}
 
 int build_macro_tables(const double *V, int n, const hhg_op_desc &op, MacroTables &out) {
   Vec3 e[3];
@@ -174,6 +204,9 @@ int build_macro_tables(const double *V, int n, const hhg_op_desc &op, MacroTable
     Vec3 g[4];
     double vol;
     p1_grads(P, g, vol);
+    out.st.vol = vol;
+    for (int c = 0; c < 4; ++c)
+      for (int q = 0; q < 3; ++q) out.st.grad[t][c][q] = g[c][q];
     for (int c = 0; c < 4; ++c) {
       B1[t][c] = form_block(g[0], g[c], vol, op.mu1, op.lam1);
       B0[t][c] = form_block(g[0], g[c], vol, op.mu0, op.lam0);
@@ -183,6 +216,10 @@ int build_macro_tables(const double *V, int n, const hhg_op_desc &op, MacroTable
           out.ec.b0[t][c][3 * m + l] = B0[t][c][m][l];
         }
     }
+  }
+  {
+    int rc = build_strain_tables(e, out.st);
+    if (rc) return rc;
   }
   // per direction: sums over the elements of the edge (origin, d)
   Mat3 Ssym[NDIR], A0[NDIR];
@@ -338,6 +375,9 @@ void free_ctx(hhg_ctx *h) {
   dfree(h->d_grp_ptr);
   dfree(h->d_grp_slot);
   dfree(h->d_flags);
+  dfree(h->d_agrp_ptr);
+  dfree(h->d_agrp_slot);
+  dfree(h->d_stc);
   for (auto &r : h->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -366,6 +406,7 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   h->minfo.resize(M);
   h->sc64.resize(M);
   h->ec64.resize(M);
+  h->stc.resize(M);
   int64_t off = 0;
   double gscale = 0.0;
   for (int m = 0; m < 12 * M; ++m) gscale = std::max(gscale, std::fabs(mesh->verts[m]));
@@ -398,6 +439,7 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
     if (rc) return rc;
     h->sc64[m] = tabs.sc;
     h->ec64[m] = tabs.ec;
+    h->stc[m] = tabs.st;
   }
   h->n_nodes = off;
 
@@ -517,6 +559,15 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
         multi.push_back(sl);
       }
     }
+    std::vector<std::vector<int64_t>> all;
+    for (auto &g : groups)
+      if (g.second.size() > 1) all.push_back(g.second);
+    std::sort(all.begin(), all.end());
+    h->agrp_ptr.assign(1, 0);
+    for (auto &sl : all) {
+      for (int64_t q : sl) h->agrp_slot.push_back(q);
+      h->agrp_ptr.push_back((int64_t)h->agrp_slot.size());
+    }
     std::sort(multi.begin(), multi.end());
     for (auto &sl : multi) {
       for (int64_t s : sl) gslot.push_back(s);
@@ -530,6 +581,8 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
     }
   }
   h->n_grp = (int64_t)gptr.size() - 1;
+  if (h->agrp_ptr.empty()) h->agrp_ptr.assign(1, 0);
+  h->n_agrp = (int64_t)h->agrp_ptr.size() - 1;
   // boundary-row kernel input: non-Dirichlet boundary slots grouped by macro,
   // each macro padded to whole blocks so that a block sees a single macro
   std::vector<int32_t> bijk, bblk;
@@ -640,6 +693,9 @@ int ensure_device(hhg_ctx *h) {
   if ((rc = upload(&h->d_grp_ptr, h->grp_ptr.data(), h->grp_ptr.size()))) return rc;
   if ((rc = upload(&h->d_grp_slot, h->grp_slot.data(), h->grp_slot.size()))) return rc;
   if ((rc = upload(&h->d_flags, h->flags.data(), h->flags.size()))) return rc;
+  if ((rc = upload(&h->d_agrp_ptr, h->agrp_ptr.data(), h->agrp_ptr.size()))) return rc;
+  if ((rc = upload(&h->d_agrp_slot, h->agrp_slot.data(), h->agrp_slot.size()))) return rc;
+  if ((rc = upload(&h->d_stc, h->stc.data(), h->stc.size()))) return rc;
   HHG_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   HHG_HIP(hipStreamCreateWithFlags(&h->solve_stream, hipStreamNonBlocking));
   HHG_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));

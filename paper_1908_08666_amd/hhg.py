@@ -168,6 +168,25 @@ class Mesh:
             L.check(rc)
         return x, out
 
+    # ------------------------------------------------------- viscosity
+    def nodal_viscosity(self, u, eta0=1.0, eta_inf=1e-3, kappa=1.0, r=-0.25, k=None,
+                        workspace=None, stream=None):
+        """Carreau viscosity at the nodes from velocity u (``hhg_nodal_viscosity``)."""
+        import torch
+        N = self.n_nodes
+        if k is None:
+            k = torch.empty(N, dtype=torch.float64, device=u.device)
+        nb = ctypes.c_size_t()
+        L.check(self._lib.hhg_viscosity_workspace_bytes(self._h, ctypes.byref(nb)))
+        if workspace is None or workspace.numel() * workspace.element_size() < nb.value:
+            workspace = torch.empty(int(nb.value) // 8 + 2, dtype=torch.float64, device=u.device)
+        law = L.Carreau(eta0, eta_inf, kappa, r)
+        L.check(self._lib.hhg_nodal_viscosity(self._h, _dev_ptr(u, (3, N), torch.float64),
+                                              ctypes.byref(law), _dev_ptr(k, (N,), torch.float64),
+                                              ctypes.c_void_p(workspace.data_ptr()),
+                                              _stream_ptr(stream)))
+        return k
+
     # ------------------------------------------------------------ tracing
     def profile_enable(self, on=True):
         L.check(self._lib.hhg_profile_enable(self._h, 1 if on else 0))

@@ -1,0 +1,80 @@
+"""Pins of the oracle's nodal strain rate and Carreau law (Sec. 3, eq. carreau)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import strain as ST
+from oracle.mesh import MacroMesh
+
+
+@pytest.fixture(scope="module")
+def mesh():
+    return MacroMesh(W.cube24(), 2)
+
+
+def test_affine_field_exact_everywhere(mesh):
+    rng = np.random.default_rng(0)
+    A = rng.normal(size=(3, 3))
+    c = rng.normal(size=3)
+    u = mesh.xyz @ A.T + c
+    G = ST.nodal_gradients(mesh, u)
+    np.testing.assert_allclose(G, np.broadcast_to(A, G.shape), atol=1e-12)
+
+
+def test_quadratic_field_exact_in_macro_interiors():
+    """Sec. 3: on the symmetric interior patch the affine fit has the gradient
+    of the quadratic fit, i.e. the exact gradient of a quadratic field."""
+    mesh = MacroMesh(W.unit_tet(), 3)
+    x = mesh.xyz
+    u = np.column_stack([x[:, 0] ** 2 + 3 * x[:, 1] * x[:, 2], x[:, 1] ** 2 - x[:, 0] * x[:, 2],
+                         2 * x[:, 2] ** 2 + x[:, 0] * x[:, 1]])
+    gx = np.zeros((mesh.n_nodes, 3, 3))
+    gx[:, 0] = np.column_stack([2 * x[:, 0], 3 * x[:, 2], 3 * x[:, 1]])
+    gx[:, 1] = np.column_stack([-x[:, 2], 2 * x[:, 1], -x[:, 0]])
+    gx[:, 2] = np.column_stack([x[:, 1], x[:, 0], 4 * x[:, 2]])
+    G = ST.nodal_gradients(mesh, u)
+    inner = ~mesh.interface
+    np.testing.assert_allclose(G[inner], gx[inner], atol=1e-12)
+    assert np.abs(G[~inner] - gx[~inner]).max() > 1e-3     # boundary average is not exact
+
+
+def test_smooth_field_converges():
+    """Interior least-squares gradients of a smooth field converge at second
+    order (the fit is exact for quadratics)."""
+    def field(x):
+        return np.column_stack([np.sin(x[:, 0] + 2 * x[:, 1]), np.cos(x[:, 2] - x[:, 0]),
+                                np.sin(x[:, 1] * x[:, 2])])
+
+    def grad(x):
+        g = np.zeros((x.shape[0], 3, 3))
+        c0 = np.cos(x[:, 0] + 2 * x[:, 1])
+        s1 = np.sin(x[:, 2] - x[:, 0])
+        c2 = np.cos(x[:, 1] * x[:, 2])
+        g[:, 0, 0], g[:, 0, 1] = c0, 2 * c0
+        g[:, 1, 0], g[:, 1, 2] = s1, -s1
+        g[:, 2, 1], g[:, 2, 2] = x[:, 2] * c2, x[:, 1] * c2
+        return g
+
+    errs = []
+    for L in (3, 4):
+        mesh = MacroMesh(W.kuhn6(), L)
+        G = ST.nodal_gradients(mesh, field(mesh.xyz))
+        inner = ~mesh.interface
+        errs.append(np.abs(G[inner] - grad(mesh.xyz)[inner]).max())
+    assert errs[0] / errs[1] > 3.0
+
+
+def test_carreau_law():
+    eps2 = np.array([0.0, 1e-3, 1.0, 1e3, 1e12])
+    mu = ST.carreau(eps2, 1.0, 1e-3, 1.0, -0.25)
+    assert mu[0] == 1.0
+    assert np.all(np.diff(mu) < 0)
+    assert abs(mu[-1] - 1e-3) < 1e-3
+    # shear thinning reduces to the Newtonian case for r = 0
+    assert np.all(ST.carreau(eps2, 2.0, 1e-3, 5.0, 0.0) == 2.0)
+
+
+def test_strain_rate_of_rotation_is_zero():
+    G = np.zeros((4, 3, 3))
+    G[:, 0, 1], G[:, 1, 0] = 1.0, -1.0
+    assert np.all(ST.strain_rate_squared(G) == 0)
