@@ -316,7 +316,8 @@ __global__ __launch_bounds__(256) void k_diag(const MacroInfo *__restrict__ minf
   for (int q = 0; q < 6; ++q) D[q * N + slot] = d[q];
 }
 
-// Sum of the diagonal-block partials over the copies of interface nodes.
+// Sum of the diagonal-block partials over the copies of interface nodes:
+// one thread per (group, entry), so the grid must cover 6 * ng threads.
 __global__ void k_group_sum6(const int64_t *__restrict__ ptr, const int64_t *__restrict__ slots,
                              int64_t ng, double *__restrict__ D, int64_t N) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -578,8 +579,8 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
     hipLaunchKernelGGL(k_diag, dim3((maxn + 255) / 256, h->n_macro), dim3(256), 0, st, h->d_minfo,
                        h->d_sc64, h->d_ec64, k, o->method, N, P64);
     if (h->n_grp > 0)
-      hipLaunchKernelGGL(k_group_sum6, grid_for(6 * h->n_grp), dim3(256), 0, st, h->d_grp_ptr,
-                         h->d_grp_slot, h->n_grp, P64, N);
+      hipLaunchKernelGGL(k_group_sum6, dim3((unsigned)((6 * h->n_grp + 255) / 256)), dim3(256), 0, st,
+                         h->d_grp_ptr, h->d_grp_slot, h->n_grp, P64, N);
     hipLaunchKernelGGL(k_invert, grid_for(N), dim3(256), 0, st, P64, h->d_flags, N,
                        o->precond == HHG_PRECOND_NONE ? 1 : 0);
     hipLaunchKernelGGL(k_zero_dirichlet<double>, grid_for(N), dim3(256), 0, st, x, h->d_flags, N);

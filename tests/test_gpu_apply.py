@@ -182,3 +182,22 @@ def test_full_size_kuhn6_level7_sampled_rows():
         err = rel_err(y[rows], ref[rows])
         print(f"  level-7 sampled rows {dtype}: {err:.3e}", flush=True)
         assert err <= TOL[dtype]
+
+
+def test_full_size_cube24_level7_sampled_rows():
+    """24 macros at level 7 (8,787,480 slots): the largest single-mesh case.
+    Sampled unknown rows, half of them on macro interfaces where up to 24
+    copies meet, recomputed by the oracle one by one."""
+    lib, orc, s2n = setup_case(W.cube24(), 7, dict(mu1=1.0))
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(3, 0), 8, 1.5)
+    x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(3, 1)).reshape(-1, 3)
+    rng = np.random.default_rng(12)
+    u = orc.unknown
+    iface = u[orc.interface[u]]
+    rows = np.unique(np.concatenate([rng.choice(u, 400, replace=False),
+                                     rng.choice(iface, 400, replace=False)]))
+    y = gather_consistent(run_apply(lib, s2n, x, k, torch.float64), s2n, orc.n_nodes)
+    ref = oracle_apply(orc, k, dict(mu1=1.0), x, "scaled", torch.float64, rows=rows)
+    err = rel_err(y[rows], ref[rows])
+    print(f"  cube24 level-7 sampled rows: {err:.3e}", flush=True)
+    assert err <= TOL[torch.float64]

@@ -117,3 +117,25 @@ def test_solver_bitwise_reproducible():
     x1, i1, *_ = solve_case(lib, orc, s2n, EFORM, k, b, solver="ir32", rtol=1e-9)
     x2, i2, *_ = solve_case(lib, orc, s2n, EFORM, k, b, solver="ir32", rtol=1e-9)
     assert np.array_equal(x1, x2) and i1["iterations"] == i2["iterations"]
+
+
+def test_cube24_level7_block_jacobi_beats_plain_cg():
+    """Regression: at this size the interface groups outnumber one capped
+    launch grid; every diagonal block must still be summed over its copies,
+    else the preconditioner is wrong and CG stalls."""
+    from paper_1908_08666_amd import Mesh
+    lib = Mesh(W.cube24(), 7, mu1=1.0)
+    fl = torch.from_numpy(lib.flags()).cuda()
+    k = torch.ones(lib.n_nodes, dtype=torch.float64, device="cuda")
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x0 = (torch.rand(3, lib.n_nodes, generator=g, dtype=torch.float64) - 0.5).cuda()
+    # b = A x0 is consistent (every copy of a node carries the same value)
+    # and zero on Dirichlet rows
+    b = lib.apply_scaled(x0, k)
+    assert torch.all(b[:, (fl & 1) > 0] == 0)
+    _, i_bj = lib.solve(b, k, rtol=1e-6, maxit=3000, check_every=16, raise_on_status=False)
+    _, i_no = lib.solve(b, k, rtol=1e-6, maxit=3000, check_every=16, raise_on_status=False,
+                        precond="none")
+    print(f"  block Jacobi {i_bj}\n  none {i_no}", flush=True)
+    assert i_bj["status"] == "HHG_OK" and i_no["status"] == "HHG_OK"
+    assert i_bj["rel_residual"] <= 1e-6 and i_bj["iterations"] < i_no["iterations"]
