@@ -34,6 +34,33 @@ BYTES_PER_INTERIOR_NODE = {"f64": 56.0, "f32": 28.0}   # x (3) + k (1) read, y (
 N_SETS = 5
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_interior_f64_kuhn6_level7_traffic.md")
+
+
+def traffic_record():
+    """Counter-measured HBM bytes per interior-kernel launch (FETCH_SIZE and
+    WRITE_SIZE passes scaled by a plain copy), valid only while the kernel
+    sources are the ones the counters were taken on."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_RECORD).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256()
+    try:
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    return rec if h.hexdigest() == rec["source_sha256"] else None
+
+
 def consistent_random(mesh, rng, shape_first):
     """U(-1,1) values per distinct node, copied to every copy slot."""
     import numpy as np
@@ -132,6 +159,8 @@ def main():
     ap.add_argument("--carreau-level", type=int, default=7)
     ap.add_argument("--carreau", action="store_true",
                     help="also run the 24-macro Carreau eps-operator workload (viscosity + solves)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB FP64 buffer 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
@@ -145,6 +174,16 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes,
+                                               "launches": 10}}), flush=True)
+        return
     mu, lam = W.eform_weights()
     mesh = Mesh(W.kuhn6(), args.level, mu1=mu, lam1=lam)
     n = 1 << args.level
@@ -195,8 +234,12 @@ def main():
     avg_int_ms = int_ms / max(nl, 1)
     alg_bytes = BYTES_PER_INTERIOR_NODE["f64"] * interior_rows
     achieved = alg_bytes / (avg_int_ms * 1e-3) / 1e9
+    rec = traffic_record() if args.level == 7 else None
+    traffic = rec["traffic_bytes_per_launch"] if rec else None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    traffic_over_algorithmic=round(traffic / alg_bytes, 3) if traffic else None,
                     kernel="k_interior<double, scaled>",
                     avg_kernel_ms=round(avg_int_ms, 5),
                     bytes_per_launch=int(alg_bytes),
