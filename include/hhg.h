@@ -227,6 +227,64 @@ int hhg_viscosity_workspace_bytes(hhg_handle h, size_t *bytes);
 int hhg_nodal_viscosity(hhg_handle h, const double *u, const hhg_carreau *law, double *k,
                         void *workspace, void *stream);
 
+/* ---------------------------------------------------------------- batching
+ * Many macros, or many independent problems of uneven level (coupling
+ * HHG_INDEPENDENT), share one interior launch: the work list holds slabs of
+ * 256 in-plane positions over a run of planes of one macro, ordered so that
+ * item q runs on XCD q % 8.  (Not in the paper; its macro-interior sweep,
+ * Sec. 4, is the unit of work here.)
+ *
+ * hhg_autotune: times the interior kernel of `method` in precision `prec` on
+ * the caller's x and k (device, as for hhg_apply_scaled), `reps` launches per
+ * candidate after one warm-up: per level, over slab depths 1, 2, 4, ... planes
+ * per item on that level's macros alone; then over the whole list, over grids
+ * of one workgroup per item or a persistent grid of 1..4 x (compute units)
+ * resident workgroups striding the list.  The fastest choices are kept in
+ * the handle for every later apply, residual and solve; results do not
+ * depend on them (every row is computed by one thread the same way).  y is
+ * scratch during tuning and holds A x on return.  Synchronizes `stream`.
+ * Graphs from hhg_graph_create are dropped (their ids become invalid).
+ * Errors: as hhg_apply_scaled, HHG_EINVAL for reps outside 1..1000 or a null
+ * report, HHG_EHIP for a runtime failure (the previous configuration stays). */
+typedef struct {
+  int32_t n_levels;          /* distinct levels, ascending in level[]        */
+  int32_t persist_blocks;    /* chosen grid: 0 = one workgroup per item      */
+  int32_t level[8];
+  int32_t slab[8];           /* chosen planes per work item                  */
+  int32_t macros[8];         /* macros of the level                          */
+  int64_t rows[8];           /* macro-interior rows of the level             */
+  double ms[8];              /* interior launch over the level's macros alone */
+  double ms_total;           /* interior launch over all macros, chosen grid */
+  int32_t candidates;        /* configurations timed                         */
+  int32_t pad;
+} hhg_tune_report;
+
+int hhg_autotune(hhg_handle h, int32_t prec, int32_t method, const void *x, const void *k, void *y,
+                 int32_t reps, hhg_tune_report *report, void *stream);
+
+/* hhg_set_tuning: adopts a tuning record (as filled by hhg_autotune, or
+ * written by the caller) without timing anything: slab[q] planes per work
+ * item for macros of level[q] (q < n_levels; 0 or an absent level keeps the
+ * default depth of 4), and the grid (persist_blocks 0: one workgroup per work
+ * item; else a multiple of 8 up to 65536 resident workgroups striding the
+ * list).  Other fields are ignored.  Waits for all queued device work, then
+ * replaces the handle's work list; graphs from hhg_graph_create are dropped.
+ * Results do not depend on the record.  Errors: HHG_EINVAL for a null record,
+ * levels outside 2..9, slabs outside 0..1024 or an invalid grid; HHG_EHIP.  */
+int hhg_set_tuning(hhg_handle h, const hhg_tune_report *tuning);
+
+/* hhg_graph_create: runs one checked apply y = A x (prec, method as in
+ * hhg_residual) after all queued device work, then captures `count`
+ * (1..1024) applies on the same device pointers into a HIP graph owned by
+ * the handle and returns its id.  hhg_graph_launch replays it on `stream`
+ * (asynchronous; the pointers must stay valid).  hhg_graph_destroy frees it;
+ * hhg_destroy and hhg_autotune free all.  Errors: HHG_EINVAL for bad
+ * arguments or an unknown id, HHG_EHIP for a capture or launch failure.     */
+int hhg_graph_create(hhg_handle h, int32_t prec, int32_t method, const void *x, const void *k,
+                     void *y, int32_t count, int32_t *graph_id);
+int hhg_graph_launch(hhg_handle h, int32_t graph_id, void *stream);
+int hhg_graph_destroy(hhg_handle h, int32_t graph_id);
+
 /* Kernel timing (tracing aid, not needed for results).  While enabled,
  * every kernel the library launches is bracketed by a pair of HIP events on
  * the launch stream.  hhg_profile_read synchronizes those events and returns,

@@ -56,6 +56,14 @@ class Carreau(ctypes.Structure):
                 ("r", ctypes.c_double)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
+                ("level", ctypes.c_int32 * 8), ("slab", ctypes.c_int32 * 8),
+                ("macros", ctypes.c_int32 * 8), ("rows", ctypes.c_int64 * 8),
+                ("ms", ctypes.c_double * 8), ("ms_total", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class HHGError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -82,6 +90,11 @@ SIGNATURES = {
                      ctypes.c_int),
     "hhg_viscosity_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hhg_nodal_viscosity": ([_VP, _VP, ctypes.POINTER(Carreau), _VP, _VP, _VP], ctypes.c_int),
+    "hhg_autotune": ([_VP, _I32, _I32, _VP, _VP, _VP, _I32, ctypes.POINTER(TuneReport), _VP], ctypes.c_int),
+    "hhg_set_tuning": ([_VP, ctypes.POINTER(TuneReport)], ctypes.c_int),
+    "hhg_graph_create": ([_VP, _I32, _I32, _VP, _VP, _VP, _I32, ctypes.POINTER(_I32)], ctypes.c_int),
+    "hhg_graph_launch": ([_VP, _I32, _VP], ctypes.c_int),
+    "hhg_graph_destroy": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hhg_last_error": ([], ctypes.c_char_p),

@@ -29,7 +29,9 @@ struct hhg_ctx {
   std::vector<int64_t> grp_ptr, grp_slot;    // non-Dirichlet copy groups
   std::vector<int64_t> agrp_ptr, agrp_slot;  // all copy groups
   int wl_max = 0;                            // LDS window entries per plane
-  int planes_per_item = 4;
+  int planes_per_item = 4;                   // default slab depth (planes per work item)
+  int slab_by_level[hhg::MAX_LEVEL + 1] = {};  // tuned slab depth per level (0: default)
+  int persist_blocks = 0;                    // 0: one workgroup per item; else resident grid size
   int chunk = 256;                           // positions per interior work item
   bool stage_dma = false;                    // interior staging by LDS-DMA loads (opt-in)
   bool serial_apply = false;                 // boundary rows on the caller's stream too
@@ -60,6 +62,14 @@ struct hhg_ctx {
   void *h_state = nullptr;                   // pinned host mirror of the solver state
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
+  // captured applies (hhg_graph_*): id -> executable graph
+  struct GraphRec {
+    int32_t id;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphRec> graphs;
+  int32_t next_graph_id = 1;
+
   // kernel timing (hhg_profile_*)
   struct ProfRec {
     int kid;
@@ -74,6 +84,13 @@ struct hhg_ctx {
 
 namespace hhg {
 int ensure_device(hhg_ctx *h);
+// Interior work list over the given macros: slabs of slab[level] planes (or
+// the default depth), 256-position chunks, interleaved so that item q runs on
+// XCD q % NXCD with each XCD holding a contiguous stretch of the natural
+// (macro, plane range, chunk) order.  Also returns the LDS window length.
+void build_work(const hhg_ctx *h, const std::vector<int> &macros, const int *slab,
+                std::vector<WorkItem> &out, int &wl_max);
+void free_graphs(hhg_ctx *h);
 
 // Brackets one kernel launch with events when profiling is enabled.
 class ProfScope {

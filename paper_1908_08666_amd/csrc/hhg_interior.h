@@ -100,18 +100,17 @@ __device__ __forceinline__ void node_rows(const Node4<T> &c, const Node4<T> (&nb
   }
 }
 
+// One work item (a slab of TPB positions over planes [ka, kb) of one macro)
+// computed by the whole workgroup; every thread must call it (barriers).
 template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
-__global__ __launch_bounds__(TPB) void k_interior(
+__device__ __forceinline__ void interior_item(
+    const WorkItem w, unsigned char *smem_raw,
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
-    const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
+    const ElemConst<T> *__restrict__ ecs,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
     T *__restrict__ y, int64_t nn, int wl) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   Pair<T> *bufA = reinterpret_cast<Pair<T> *>(smem_raw);   // 3 planes of (x0, x1)
   Pair<T> *bufB = bufA + 3 * wl;                             // 3 planes of (x2, k)
-
-  const WorkItem w = work[blockIdx.x];
-  if (w.macro < 0) return;                  // padding item of the XCD-aware order
   const MacroInfo mi = minfo[w.macro];
   const int n = mi.n;
   const int tid = threadIdx.x;
@@ -223,6 +222,41 @@ __global__ __launch_bounds__(TPB) void k_interior(
     }
     __syncthreads();
     if (more) put(kk + 2);               // overwrites the slot of plane kk-1
+    __syncthreads();
+  }
+}
+
+// One workgroup per work item.
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+__global__ __launch_bounds__(TPB) void k_interior(
+    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
+    const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
+    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
+    T *__restrict__ y, int64_t nn, int wl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const WorkItem w = work[blockIdx.x];
+  if (w.macro < 0) return;                  // padding item of the XCD-aware order
+  interior_item<T, METHOD, RESID, CORR, A0, NW, TPB>(w, smem_raw, minfo, scs, ecs, x, kc, f, y,
+                                                     nn, wl);
+}
+
+// Persistent form: a grid of resident workgroups walks the work list with a
+// fixed stride (item q goes to workgroup q mod gridDim.x), so with a grid
+// that is a multiple of the XCD count every item keeps the XCD that the
+// list's order assigns it.  Every workgroup leaves after at most
+// ceil(n_work / gridDim.x) items.
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+__global__ __launch_bounds__(TPB) void k_interior_persist(
+    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
+    const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work, int n_work,
+    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
+    T *__restrict__ y, int64_t nn, int wl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  for (int q = blockIdx.x; q < n_work; q += gridDim.x) {
+    const WorkItem w = work[q];
+    if (w.macro >= 0)                       // block-uniform
+      interior_item<T, METHOD, RESID, CORR, A0, NW, TPB>(w, smem_raw, minfo, scs, ecs, x, kc, f,
+                                                         y, nn, wl);
     __syncthreads();
   }
 }
@@ -376,12 +410,21 @@ template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TP
 int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
   const int wl = h->wl_max;
   const size_t lds = 6 * (size_t)wl * sizeof(Pair<T>);
-  auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB>;
-  if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
-  hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
-                     ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
+  if (h->persist_blocks > 0) {
+    auto kern = k_interior_persist<T, METHOD, RESID, CORR, A0, NW, TPB>;
+    if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(std::min(h->persist_blocks, h->n_work)), dim3(TPB), lds, st,
+                       h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_work, h->n_work, x, k, f, y,
+                       h->n_nodes, wl);
+  } else {
+    auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB>;
+    if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
+                       ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
+  }
   HHG_HIP(hipGetLastError());
   return HHG_OK;
 }

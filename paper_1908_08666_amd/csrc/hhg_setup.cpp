@@ -363,6 +363,7 @@ void dfree(P *&p) {
 
 void free_ctx(hhg_ctx *h) {
   if (!h) return;
+  free_graphs(h);
   dfree(h->d_minfo);
   dfree(h->d_sc64);
   dfree(h->d_sc32);
@@ -619,11 +620,32 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   const char *envd = std::getenv("HHG_STAGE_DMA");
   h->stage_dma = envd && std::atoi(envd) == 1;
   h->chunk = 256;
+  {
+    std::vector<int> all(M);
+    for (int m = 0; m < M; ++m) all[m] = m;
+    build_work(h, all, nullptr, h->work, h->wl_max);
+  }
+  h->n_work = (int)h->work.size();
+
+  h->bijk = std::move(bijk);
+  h->bblk = std::move(bblk);
+  h->dslot = std::move(dslot);
+  h->grp_ptr = std::move(gptr);
+  h->grp_slot = std::move(gslot);
+  return HHG_OK;
+}
+
+}  // namespace
+
+void build_work(const hhg_ctx *h, const std::vector<int> &macros, const int *slab,
+                std::vector<WorkItem> &out, int &wl_max) {
   const int CH = h->chunk;
   std::vector<WorkItem> natural;
-  int wl_max = 0;
-  for (int m = 0; m < M; ++m) {
+  wl_max = 0;
+  for (int m : macros) {
     const int n = h->minfo[m].n;
+    const int lev = h->minfo[m].level;
+    const int depth = std::max(1, (slab && slab[lev] > 0) ? slab[lev] : h->planes_per_item);
     const int64_t npos = tri(n - 1);  // interior positions live below T(n-1)
     const int nchunk = (int)((npos + CH - 1) / CH);
     std::vector<int> kmax(nchunk);
@@ -637,32 +659,19 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
       kmax[c] = (int)(n - 1 - std::max<int64_t>(2, s_lo));
       kmax_all = std::max(kmax_all, kmax[c]);
     }
-    for (int ka = 1; ka <= kmax_all; ka += h->planes_per_item)
+    for (int ka = 1; ka <= kmax_all; ka += depth)
       for (int c = 0; c < nchunk; ++c)
-        if (ka <= kmax[c]) natural.push_back({m, c, ka, std::min(ka + h->planes_per_item, kmax[c] + 1)});
+        if (ka <= kmax[c]) natural.push_back({m, c, ka, std::min(ka + depth, kmax[c] + 1)});
   }
-  h->wl_max = wl_max;
   // workgroup g runs on XCD g % NXCD: give every XCD a contiguous stretch of
   // the natural order so that neighbouring chunks share its L2
-  {
-    const size_t per = (natural.size() + NXCD - 1) / NXCD;
-    h->work.assign(per * NXCD, WorkItem{-1, 0, 0, 0});
-    for (size_t q = 0; q < natural.size(); ++q) {
-      const size_t x = q / per, r = q % per;
-      h->work[r * NXCD + x] = natural[q];
-    }
+  const size_t per = (natural.size() + NXCD - 1) / NXCD;
+  out.assign(per * NXCD, WorkItem{-1, 0, 0, 0});
+  for (size_t q = 0; q < natural.size(); ++q) {
+    const size_t x = q / per, r = q % per;
+    out[r * NXCD + x] = natural[q];
   }
-  h->n_work = (int)h->work.size();
-
-  h->bijk = std::move(bijk);
-  h->bblk = std::move(bblk);
-  h->dslot = std::move(dslot);
-  h->grp_ptr = std::move(gptr);
-  h->grp_slot = std::move(gslot);
-  return HHG_OK;
 }
-
-}  // namespace
 
 // Upload the constant tables to the current device at the first device call.
 int ensure_device(hhg_ctx *h) {

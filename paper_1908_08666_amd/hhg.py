@@ -187,6 +187,53 @@ class Mesh:
                                               _stream_ptr(stream)))
         return k
 
+    # ------------------------------------------------------------ batching
+    def autotune(self, x, k, y=None, method="scaled", reps=5, stream=None):
+        """Pick slab depth per level and the launch grid (``hhg_autotune``);
+        returns (y = A x, report dict)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        prec, px, pk, py = self._vec_args(x, k, y)
+        rep = L.TuneReport()
+        m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
+        L.check(self._lib.hhg_autotune(self._h, prec, m, px, pk, py, int(reps), ctypes.byref(rep),
+                                       _stream_ptr(stream)))
+        levels = []
+        for q in range(rep.n_levels):
+            levels.append(dict(level=rep.level[q], slab=rep.slab[q], macros=rep.macros[q],
+                               rows=int(rep.rows[q]), ms=rep.ms[q]))
+        return y, dict(levels=levels, persist_blocks=rep.persist_blocks, ms_total=rep.ms_total,
+                       candidates=rep.candidates)
+
+    def set_tuning(self, levels=None, slabs=None, persist_blocks=0):
+        """Adopt slab depths per level and a grid without timing (``hhg_set_tuning``)."""
+        rep = L.TuneReport()
+        levels = list(levels or [])
+        slabs = list(slabs or [])
+        if len(levels) != len(slabs) or len(levels) > 8:
+            raise ValueError("levels and slabs: equal length, at most 8")
+        rep.n_levels = len(levels)
+        for q, (lv, sb) in enumerate(zip(levels, slabs)):
+            rep.level[q] = int(lv)
+            rep.slab[q] = int(sb)
+        rep.persist_blocks = int(persist_blocks)
+        L.check(self._lib.hhg_set_tuning(self._h, ctypes.byref(rep)))
+
+    def graph_create(self, x, k, y, method="scaled", count=1):
+        """Capture ``count`` applies y = A x in a HIP graph (``hhg_graph_create``)."""
+        prec, px, pk, py = self._vec_args(x, k, y)
+        m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
+        gid = ctypes.c_int32()
+        L.check(self._lib.hhg_graph_create(self._h, prec, m, px, pk, py, int(count), ctypes.byref(gid)))
+        return int(gid.value)
+
+    def graph_launch(self, graph_id, stream=None):
+        L.check(self._lib.hhg_graph_launch(self._h, int(graph_id), _stream_ptr(stream)))
+
+    def graph_destroy(self, graph_id):
+        L.check(self._lib.hhg_graph_destroy(self._h, int(graph_id)))
+
     # ------------------------------------------------------------ tracing
     def profile_enable(self, on=True):
         L.check(self._lib.hhg_profile_enable(self._h, 1 if on else 0))

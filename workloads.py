@@ -97,6 +97,16 @@ def batch_field_params(n_problems: int = 256, config_id: int = 4):
     return modes, amps
 
 
+def batch_coefficients(local_xyz, config_id: int = 4) -> list:
+    """One coefficient field per independent problem: k = exp(g_p) with g_p a
+    Fourier field of that problem's mode count and amplitude
+    (``batch_field_params``), drawn from its own seed; ``local_xyz`` lists the
+    node coordinates of each problem."""
+    modes, amps = batch_field_params(len(local_xyz), config_id)
+    return [exp_fourier_coefficient(xyz, rng_for(config_id, 1000 + p), int(modes[p]), float(amps[p]))
+            for p, xyz in enumerate(local_xyz)]
+
+
 # -------------------------------------------------------------- nodal fields
 
 def sine_coefficient(xyz: np.ndarray) -> np.ndarray:
