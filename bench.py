@@ -63,14 +63,8 @@ def traffic_record():
 
 def consistent_random(mesh, rng, shape_first):
     """U(-1,1) values per distinct node, copied to every copy slot."""
-    import numpy as np
-    fl = mesh.flags()
-    xyz = mesh.coords().T
-    owners = np.nonzero(fl & 2)[0]
-    from scipy.spatial import cKDTree
-    _, idx = cKDTree(xyz[owners]).query(xyz)
-    vals = rng.uniform(-1.0, 1.0, size=(shape_first, owners.shape[0]))
-    return np.ascontiguousarray(vals[:, idx])
+    import workloads as W
+    return W.consistent_uniform(mesh.coords().T, (mesh.flags() & 2) > 0, rng, shape_first)
 
 
 def cpu_baseline(level, rows_sample, seed=0):
@@ -146,6 +140,73 @@ def carreau_workload(level, dev, solve=True, maxit=60000):
     return out
 
 
+def learned_workload(dev, level=6, n_records=20000, epochs=100, batch=2048, lr=3e-3):
+    """Learned block smoother on the 24-macro Carreau eps-operator: records
+    from the plain solver, training on the device, then FP64 solves to 1e-8
+    with block Jacobi (PCG, FCG) and with the learned blocks (FCG), and the
+    FP32 + refinement solver with either preconditioner."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1908_08666_amd import Mesh
+    from paper_1908_08666_amd import learned as LG
+    mesh = Mesh(W.cube24(), level, mu1=1.0)
+    xyz = mesh.coords().T
+    owner = (mesh.flags() & 2) > 0
+    u = torch.from_numpy(np.ascontiguousarray(
+        W.localized_velocity_field(xyz, W.rng_for(5, 0), 1e6).T)).to(dev)
+    k = mesh.nodal_viscosity(u, **W.CARREAU_DEFAULT)
+    b = torch.from_numpy(W.consistent_uniform(xyz, owner, W.rng_for(5, 1))).to(dev)
+    fl = torch.from_numpy(mesh.flags()).to(dev)
+    b[:, (fl & 1) > 0] = 0.0
+    noise = torch.from_numpy(W.consistent_uniform(xyz, owner, W.rng_for(5, 2))).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec, xs = LG.solver_pairs(mesh, k, b, noise, n_records, seed=3)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    perm = torch.randperm(n_records, generator=torch.Generator().manual_seed(0)).to(dev)
+    rec = rec[perm].contiguous()
+    net = LG.SmootherNet(W.smoother_init_weights(W.rng_for(5, 4)))
+    held = rec[-2000:]
+    l0, _ = net.loss_grad(held, held.shape[0])
+    t0 = time.perf_counter()
+    hist = net.train(rec[:-2000], n_records - 2000, epochs=epochs, batch=batch, lr=lr)
+    t_train = time.perf_counter() - t0
+    l1, _ = net.loss_grad(held, held.shape[0])
+    LG.attach(mesh, net)
+    out = dict(level=level, macros=mesh.n_macro, unknown_dofs=3 * mesh.n_unknown,
+               viscosity_min=float(k.min()), viscosity_max=float(k.max()),
+               contrast=float(k.max() / k.min()), records=n_records, epochs=epochs, batch=batch,
+               pairs_seconds=round(t_pairs, 3), train_seconds=round(t_train, 3),
+               train_loss_first_last=[float(hist[0]), float(hist[-1])],
+               heldout_loss_block_jacobi=round(l0, 5), heldout_loss_learned=round(l1, 5))
+    ws = None
+    xn = float(torch.linalg.norm(xs))
+    for name, opts in (("pcg64_block_jacobi", dict(solver="cg64", precond="block_jacobi")),
+                       ("fcg64_block_jacobi", dict(solver="fcg64", precond="block_jacobi")),
+                       ("fcg64_learned", dict(solver="fcg64", precond="learned")),
+                       ("ir32_block_jacobi", dict(solver="ir32", precond="block_jacobi", inner_rtol=1e-2)),
+                       ("ir32_learned", dict(solver="ir32", precond="learned", inner_rtol=1e-2))):
+        nb = mesh.workspace_bytes(**opts)
+        if ws is None or ws.numel() < nb + 256:
+            ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        for rep in range(2):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = mesh.solve(b, k, x=x, workspace=ws, rtol=1e-8, check_every=16, maxit=60000,
+                                 raise_on_status=False, **opts)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        out[name] = dict(iterations=info["iterations"], outer=info["outer_iterations"],
+                         seconds=round(wall, 4), rel_residual=info["rel_residual"],
+                         status=info["status"],
+                         rel_error_vs_tight_fp64_solution=float(torch.linalg.norm(x - xs)) / xn)
+    LG.attach(mesh, None)
+    return out
+
+
 def batch_workload(dev, launches=20, count=10):
     """256 independent single-macro elasticity problems, levels uniform in
     3..6, each with its own coefficient field: FP32 apply over the whole
@@ -218,6 +279,8 @@ def main():
                     help="also run the 24-macro Carreau eps-operator workload (viscosity + solves)")
     ap.add_argument("--batch", action="store_true",
                     help="also run 256 independent uneven-level problems in one tuned, graph-replayed launch")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the learned block smoother and compare FCG solves (24 macros, level 6)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 buffer 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -361,6 +424,11 @@ def main():
         sets64 = sets32 = None
         torch.cuda.empty_cache()
         extra["batch256_independent"] = batch_workload(dev)
+
+    if args.learned:
+        sets64 = sets32 = None
+        torch.cuda.empty_cache()
+        extra["learned_smoother_cube24"] = learned_workload(dev)
 
     if args.carreau:
         sets64 = sets32 = None

@@ -166,12 +166,20 @@ int hhg_residual(hhg_handle h, int32_t prec, int32_t method, const void *f, cons
  *               preconditioned CG with FP32 vectors, FP32 coefficient and
  *               FP32 applies, inner dot products accumulated in FP64, run to
  *               inner_rtol relative reduction.
- * Preconditioner: HHG_PRECOND_NONE, or HHG_PRECOND_BLOCK_JACOBI (inverse of
- * the 3x3 diagonal block of the assembled operator at every node).
+ *   HHG_FCG_F64 flexible CG in FP64: as HHG_CG_F64 with the Polak-Ribiere
+ *               beta = (z+, r+ - r) / (z, r), computed from the (z, A p)
+ *               product fused into the update; for a fixed symmetric positive
+ *               definite preconditioner the iterates are those of CG.
+ * Preconditioner: HHG_PRECOND_NONE, HHG_PRECOND_BLOCK_JACOBI (inverse of
+ * the 3x3 diagonal block of the assembled operator at every node), or
+ * HHG_PRECOND_LEARNED: P = (I + M)^T D^{-1} (I + M) with D that diagonal block
+ * and M the output of the network attached by hhg_set_learned_model, fed the
+ * node's coefficient neighbourhood and averaged over the node's copies
+ * (computed once per solve; see the learned smoother section below).
  * Stopping rule: ||b - A x||_2 <= rtol ||b||_2 over the unknowns, with the
  * final residual recomputed in FP64 (reported in info->rel_residual). */
-enum hhg_solver { HHG_CG_F64 = 0, HHG_IR_F32 = 1 };
-enum hhg_precond { HHG_PRECOND_NONE = 0, HHG_PRECOND_BLOCK_JACOBI = 1 };
+enum hhg_solver { HHG_CG_F64 = 0, HHG_IR_F32 = 1, HHG_FCG_F64 = 2 };
+enum hhg_precond { HHG_PRECOND_NONE = 0, HHG_PRECOND_BLOCK_JACOBI = 1, HHG_PRECOND_LEARNED = 2 };
 
 typedef struct {
   int32_t solver;        /* hhg_solver                                        */
@@ -192,6 +200,15 @@ typedef struct {
   double rel_residual;       /* ||b - A x|| / ||b|| recomputed in FP64        */
   double seconds;            /* wall time of the solve                        */
 } hhg_solve_info;
+
+/* The preconditioner blocks a solve would use (symmetric 3x3 per slot,
+ * P device FP64 [6][n_nodes] in the order xx yy zz xy xz yz; identity for
+ * HHG_PRECOND_NONE, zero at Dirichlet slots), for operator `method` and
+ * coefficient k.  Learned blocks need an attached model; they use a scratch
+ * block of 68 n_nodes bytes that this call allocates and frees.
+ * Synchronizes `stream`.  Errors: HHG_EINVAL, HHG_EHIP.                    */
+int hhg_preconditioner(hhg_handle h, int32_t precond, int32_t method, const double *k, double *P,
+                       void *stream);
 
 /* Device workspace needed by hhg_cg_solve for these options (bytes).      */
 int hhg_workspace_bytes(hhg_handle h, const hhg_solve_opts *o, size_t *bytes);
@@ -285,6 +302,97 @@ int hhg_graph_create(hhg_handle h, int32_t prec, int32_t method, const void *x, 
 int hhg_graph_launch(hhg_handle h, int32_t graph_id, void *stream);
 int hhg_graph_destroy(hhg_handle h, int32_t graph_id);
 
+/* ------------------------------------------------------ learned smoother
+ * (Not in the paper, which smooths with Gauss-Seidel inside multigrid.)  A
+ * small network maps the coefficient neighbourhood of a node to a 3x3 block
+ * M; the preconditioner block is P = (I + M)^T D^{-1} (I + M), so M = 0 is
+ * block Jacobi (the fallback) and P stays symmetric positive definite.
+ *
+ * Features of a node copy (16, BF16): the coefficient on the node's 15-point
+ * patch (the node, then its neighbours in the order me mw mse mnw tc bc ts
+ * bn mn ms tw be tse bnw of the stencil figure, Sec. 2.4), 0 for a
+ * Dirichlet neighbour, the node's own value for a point outside the macro,
+ * divided by the mean of the 15 values (summed left to right in that order,
+ * then divided by 15); then level / 8.  Values are formed
+ * in FP64, rounded to FP32 and then to BF16, both to nearest even.
+ *
+ * Network: h = relu(W1^T f + b1) with 64 units, h rounded to BF16, and
+ * o = W2^T h + b2 (9 outputs, M row-major), BF16 weights W1 [16][64] and
+ * W2 [64][9], FP32 biases, products on the matrix cores with FP32
+ * accumulation.  Parameters as one FP32 vector of HHG_MLP_NPARAM entries:
+ * W1 (row-major [16][64]), b1 [64], W2 (row-major [64][9]), b2 [9]; the
+ * handle keeps FP32 master weights, their BF16 copies and Adam moments.
+ *
+ * Training record (HHG_SAMPLE_BYTES bytes, device): 16 BF16 features, then
+ * 12 FP32 values r'0..2, e'0..2, S xx yy zz xy xz yz, then padding, where
+ * for a node with residual r, error e and diagonal block D of a solver
+ * iterate t = trace(D)/3, S = t D^{-1}, s = sqrt(|D^{-1} r|^2 + |e|^2),
+ * r' = r / (t s), e' = e / s.  Loss of a record: |(I + M)^T S (I + M) r' -
+ * e'|^2, the error left by one smoothing step z = P r relative to the sizes
+ * of the error and of the block-Jacobi step; a batch's loss is the mean.  Gradients pass the BF16 roundings straight through.        */
+enum {
+  HHG_MLP_IN = 16,
+  HHG_MLP_HIDDEN = 64,
+  HHG_MLP_OUT = 9,
+  HHG_MLP_NPARAM = 16 * 64 + 64 + 64 * 9 + 9,
+  HHG_SAMPLE_BYTES = 128
+};
+typedef struct hhg_mlp_ctx *hhg_mlp;
+
+/* Create a model with all parameters zero (block Jacobi) on the current
+ * device / destroy it.  Errors: HHG_EINVAL (null), HHG_EHIP.               */
+int hhg_mlp_create(hhg_mlp *out);
+int hhg_mlp_destroy(hhg_mlp m);
+/* Host FP32 parameter vector in / out (HHG_MLP_NPARAM entries); set also
+ * resets the Adam moments and step count.  Synchronous.                    */
+int hhg_mlp_set_weights(hhg_mlp m, const float *w);
+int hhg_mlp_get_weights(hhg_mlp m, float *w);
+
+/* Features of every slot: feat, device, [n_nodes][16] BF16 bit patterns
+ * (uint16), from the FP64 coefficient k [n_nodes].  Asynchronous.          */
+int hhg_learn_features(hhg_handle h, const double *k, uint16_t *feat, void *stream);
+
+/* Network outputs of n feature records (device; record q starts at
+ * feat + q * stride, stride >= 16 and a multiple of 4 uint16 entries, so
+ * training records use stride HHG_SAMPLE_BYTES / 2): out, device,
+ * [n][9] FP32.  Asynchronous.                                              */
+int hhg_mlp_forward(hhg_mlp m, const uint16_t *feat, int64_t stride, int64_t n, float *out,
+                    void *stream);
+
+/* Training records of n nodes: for slots[q] (device int64, slots of
+ * distinct non-Dirichlet nodes), its features and the record values above
+ * from r and e (device FP64 [3][n_nodes]) and the operator's diagonal block
+ * for `method` and coefficient k.  samples: device, n * HHG_SAMPLE_BYTES.
+ * Allocates and frees a scratch block of 48 n_nodes bytes; synchronizes
+ * `stream`.  Errors: HHG_EINVAL (null, n < 1, misaligned), HHG_EHIP.       */
+int hhg_learn_collect(hhg_handle h, int32_t method, const double *k, const double *r,
+                      const double *e, const int64_t *slots, int64_t n, void *samples,
+                      void *stream);
+
+/* Mean loss of n records and its gradient at the current weights (host
+ * outputs: *loss, grad [HHG_MLP_NPARAM]).  Synchronizes `stream`.          */
+int hhg_mlp_loss_grad(hhg_mlp m, const void *samples, int64_t n, double *loss, float *grad,
+                      void *stream);
+
+/* Adam training on the device: `epochs` passes over the n records in
+ * consecutive mini-batches of `batch` (the last one may be shorter), one
+ * Adam step per mini-batch (bias-corrected, step count kept by the model).
+ * loss_hist (host, `epochs` entries, may be null): mean record loss of each
+ * epoch, evaluated batch by batch before that batch's step.  Synchronizes
+ * `stream`.  Errors: HHG_EINVAL for null pointers, n < 1, batch < 1,
+ * epochs < 1, lr <= 0 or betas outside [0, 1); HHG_EHIP.                   */
+typedef struct {
+  int32_t epochs;
+  int32_t batch;
+  float lr, beta1, beta2, eps;
+} hhg_train_opts;
+int hhg_mlp_train(hhg_mlp m, const void *samples, int64_t n, const hhg_train_opts *o,
+                  float *loss_hist, void *stream);
+
+/* Attach (or, with null, detach) the model used by HHG_PRECOND_LEARNED.  The
+ * handle does not own it: keep it alive while solves use it.               */
+int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
+
 /* Kernel timing (tracing aid, not needed for results).  While enabled,
  * every kernel the library launches is bracketed by a pair of HIP events on
  * the launch stream.  hhg_profile_read synchronizes those events and returns,
@@ -298,6 +406,7 @@ enum hhg_kernel_id {
   HHG_K_BOUNDARY_ROWS = 2,
   HHG_K_GROUP_SUM = 3,
   HHG_K_SOLVER_VECTOR = 4,   /* all fused vector / reduction kernels of the solvers */
+  HHG_K_LEARNED = 5,         /* features and network inference of the learned smoother */
   HHG_K_COUNT = 16
 };
 int hhg_profile_enable(hhg_handle h, int32_t on);

@@ -12,8 +12,8 @@ block-Jacobi one, written out from its definition:
   neighbours, Sec. 2.4, Fig. subtypes_and_stencil), in the direction order
   me mw mse mnw tc bc ts bn mn ms tw be tse bnw.  A neighbour that is a
   Dirichlet node contributes 0, one outside the macro repeats the node's own
-  value.  The 15 values are divided by their mean; the 16th feature is
-  level / 8.  Features are rounded FP64 -> FP32 -> BF16 (nearest even).
+  value.  The 15 values are divided by their mean (summed left to right
+  in that order, then divided by 15); the 16th feature is level / 8.  Features are rounded FP64 -> FP32 -> BF16 (nearest even).
 * Network: h = relu(W1^T f + b1) (64 units, h rounded to BF16), o = W2^T h
   + b2 (9 outputs), with BF16 weights W1 (16x64), W2 (64x9) and FP32 biases.
   M = o as a row-major 3x3 matrix.
@@ -23,9 +23,10 @@ block-Jacobi one, written out from its definition:
   positive definite whenever G is invertible.
 * Training sample: (f, r, e, S) with r, e the residual and error of an
   iterate of the plain solver at that node and S = t D^{-1}, r scaled by 1/t,
-  t = trace(D)/3, and r, e divided by |S r|.  Loss of a sample:
-  |G^T S G r - e|^2 (the error left by one smoothing step z = P r), averaged
-  over a batch.  Gradients pass the BF16 roundings straight through.
+  t = trace(D)/3, and r, e divided by s = sqrt(|D^{-1} r|^2 + |e|^2).  Loss
+  of a sample: |G^T S G r - e|^2, the error left by one smoothing step
+  z = P r relative to the size of the error and of the block-Jacobi step
+  (bounded for rough and for smooth errors alike), averaged over a batch.  Gradients pass the BF16 roundings straight through.
 * Adam update of the FP32 master weights.
 * Flexible CG (Polak-Ribiere beta), which reduces to preconditioned CG for a
   fixed symmetric positive definite preconditioner.
@@ -101,7 +102,10 @@ def macro_features(mesh, m: int, k: np.ndarray) -> np.ndarray:
             g = gid[key[tuple(nb[q])]]
             col[q] = 0.0 if mesh.dirichlet[g] else k[g]
         vals[:, 1 + d] = col
-    mean = vals.sum(1) / 15.0
+    total = vals[:, 0].copy()
+    for q in range(1, 15):                      # left to right, node first
+        total += vals[:, q]
+    mean = total / 15.0
     F = np.empty((ijk.shape[0], N_IN))
     F[:, :15] = vals / mean[:, None]
     F[:, 15] = n.bit_length() - 1
@@ -272,11 +276,11 @@ def make_samples(F, r, e, D):
     """Training records from node values: features F (n, 16), residual r and
     error e (n, 3) of a solver iterate, diagonal blocks D (n, 3, 3).
     Returns (F, r', e', S6) with t = trace(D)/3, S = t D^{-1},
-    s = |D^{-1} r|, r' = r / (t s), e' = e / s."""
+    s = sqrt(|D^{-1} r|^2 + |e|^2), r' = r / (t s), e' = e / s."""
     t = np.trace(D, axis1=1, axis2=2) / 3.0
     Dinv = np.linalg.inv(D)
     S = t[:, None, None] * Dinv
-    s = np.linalg.norm(np.einsum("nab,nb->na", Dinv, r), axis=1)
+    s = np.sqrt(np.sum(np.einsum("nab,nb->na", Dinv, r) ** 2, axis=1) + np.sum(e * e, axis=1))
     rr = r / (t * s)[:, None]
     ee = e / s[:, None]
     S6 = np.stack([S[:, 0, 0], S[:, 1, 1], S[:, 2, 2], S[:, 0, 1], S[:, 0, 2], S[:, 1, 2]], axis=1)

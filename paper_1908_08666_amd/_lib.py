@@ -17,7 +17,7 @@ HHG_IFACE_SYMMETRIC, HHG_IFACE_ROWWISE = 0, 1
 HHG_METHOD_SCALED, HHG_METHOD_ONTHEFLY = 0, 1
 HHG_K_INTERIOR_SCALED, HHG_K_INTERIOR_ONTHEFLY, HHG_K_BOUNDARY_ROWS, HHG_K_GROUP_SUM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "interior_scaled", 1: "interior_onthefly", 2: "boundary_rows", 3: "group_sum",
-                4: "solver_vector"}
+                4: "solver_vector", 5: "learned"}
 
 STATUS_NAMES = {0: "HHG_OK", -1: "HHG_EINVAL", -2: "HHG_EHIP", -3: "HHG_ENOCONV",
                 -4: "HHG_EBREAKDOWN", -5: "HHG_ENOMEM"}
@@ -47,8 +47,16 @@ class SolveInfo(ctypes.Structure):
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
-HHG_CG_F64, HHG_IR_F32 = 0, 1
-HHG_PRECOND_NONE, HHG_PRECOND_BLOCK_JACOBI = 0, 1
+HHG_CG_F64, HHG_IR_F32, HHG_FCG_F64 = 0, 1, 2
+HHG_PRECOND_NONE, HHG_PRECOND_BLOCK_JACOBI, HHG_PRECOND_LEARNED = 0, 1, 2
+HHG_MLP_IN, HHG_MLP_HIDDEN, HHG_MLP_OUT = 16, 64, 9
+HHG_MLP_NPARAM = 16 * 64 + 64 + 64 * 9 + 9
+HHG_SAMPLE_BYTES = 128
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class Carreau(ctypes.Structure):
@@ -74,6 +82,7 @@ _lib = None
 
 _VP = ctypes.c_void_p
 _I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
 _I64P = ctypes.POINTER(ctypes.c_int64)
 
 SIGNATURES = {
@@ -95,6 +104,19 @@ SIGNATURES = {
     "hhg_graph_create": ([_VP, _I32, _I32, _VP, _VP, _VP, _I32, ctypes.POINTER(_I32)], ctypes.c_int),
     "hhg_graph_launch": ([_VP, _I32, _VP], ctypes.c_int),
     "hhg_graph_destroy": ([_VP, _I32], ctypes.c_int),
+    "hhg_mlp_create": ([ctypes.POINTER(_VP)], ctypes.c_int),
+    "hhg_mlp_destroy": ([_VP], ctypes.c_int),
+    "hhg_mlp_set_weights": ([_VP, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "hhg_mlp_get_weights": ([_VP, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "hhg_learn_features": ([_VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mlp_forward": ([_VP, _VP, _I64, _I64, _VP, _VP], ctypes.c_int),
+    "hhg_learn_collect": ([_VP, _I32, _VP, _VP, _VP, _VP, _I64, _VP, _VP], ctypes.c_int),
+    "hhg_mlp_loss_grad": ([_VP, _VP, _I64, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_float), _VP], ctypes.c_int),
+    "hhg_mlp_train": ([_VP, _VP, _I64, ctypes.POINTER(TrainOpts), ctypes.POINTER(ctypes.c_float), _VP],
+                      ctypes.c_int),
+    "hhg_set_learned_model": ([_VP, _VP], ctypes.c_int),
+    "hhg_preconditioner": ([_VP, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
     "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hhg_last_error": ([], ctypes.c_char_p),

@@ -62,6 +62,8 @@ struct hhg_ctx {
   void *h_state = nullptr;                   // pinned host mirror of the solver state
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
+  hhg_mlp model = nullptr;                   // learned smoother (not owned)
+
   // captured applies (hhg_graph_*): id -> executable graph
   struct GraphRec {
     int32_t id;

@@ -4,8 +4,10 @@
 //   IR_F32  iterative refinement: FP64 residual, norm and update; inner
 //           preconditioned CG with FP32 vectors, coefficient and applies and
 //           FP64-accumulated inner products.
-// Preconditioner: inverse 3x3 diagonal blocks of the assembled operator
-// (block Jacobi).  All scalars of the iteration (alpha, beta, rho) stay on the
+//   FCG_F64 flexible CG in FP64 (Polak-Ribiere beta; equal to CG_F64 for a
+//           fixed symmetric positive definite preconditioner).
+// Preconditioners: inverse 3x3 diagonal blocks of the assembled operator
+// (block Jacobi), or those blocks reshaped by a learned network.  All scalars of the iteration (alpha, beta, rho) stay on the
 // device; the host reads the residual history every `check_every`
 // iterations, and a block of iterations is captured once in a HIP graph and
 // replayed.  Inner products run over the unknowns only: owner copies of
@@ -24,6 +26,8 @@ namespace hhg {
 
 int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
                    void *y, hipStream_t st);
+int learned_precond(hhg_ctx *h, const double *k, double *P, uint16_t *feat, float *mout,
+                    hipStream_t st);
 
 namespace {
 
@@ -76,13 +80,15 @@ __global__ __launch_bounds__(RED_TPB) void k_dot2(const T *__restrict__ a, const
   s0 = block_sum(s0, sh);
   s1 = block_sum(s1, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s0;
-    part[2 * blockIdx.x + 1] = s1;
+    part[3 * blockIdx.x] = s0;
+    part[3 * blockIdx.x + 1] = s1;
+    part[3 * blockIdx.x + 2] = 0.0;
   }
 }
 
-// x += alpha p, r -= alpha q, z = P r; partial sums of (r, z) and (r, r)
-template <typename T>
+// x += alpha p, r -= alpha q, z = P r; partial sums of (r, z) and (r, r),
+// and for the flexible variant (z, q)
+template <typename T, bool FLEX>
 __global__ __launch_bounds__(RED_TPB) void k_update(T *__restrict__ x, const T *__restrict__ p,
                                                     T *__restrict__ r, const T *__restrict__ q,
                                                     const T *__restrict__ P, T *__restrict__ z,
@@ -91,7 +97,7 @@ __global__ __launch_bounds__(RED_TPB) void k_update(T *__restrict__ x, const T *
                                                     double *__restrict__ part) {
   __shared__ double sh[RED_TPB / 64];
   const T alpha = (T)st->alpha;
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N;
        s += (int64_t)gridDim.x * blockDim.x) {
     T rv[3];
@@ -112,13 +118,17 @@ __global__ __launch_bounds__(RED_TPB) void k_update(T *__restrict__ x, const T *
     if (unknown(fl, s)) {
       s0 += (double)rv[0] * z0 + (double)rv[1] * z1 + (double)rv[2] * z2;
       s1 += (double)rv[0] * rv[0] + (double)rv[1] * rv[1] + (double)rv[2] * rv[2];
+      if (FLEX)
+        s2 += (double)z0 * q[s] + (double)z1 * q[N + s] + (double)z2 * q[2 * N + s];
     }
   }
   s0 = block_sum(s0, sh);
   s1 = block_sum(s1, sh);
+  if (FLEX) s2 = block_sum(s2, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s0;
-    part[2 * blockIdx.x + 1] = s1;
+    part[3 * blockIdx.x] = s0;
+    part[3 * blockIdx.x + 1] = s1;
+    part[3 * blockIdx.x + 2] = s2;
   }
 }
 
@@ -152,8 +162,9 @@ __global__ __launch_bounds__(RED_TPB) void k_precond(const T *__restrict__ r, co
   s0 = block_sum(s0, sh);
   s1 = block_sum(s1, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s0;
-    part[2 * blockIdx.x + 1] = s1;
+    part[3 * blockIdx.x] = s0;
+    part[3 * blockIdx.x + 1] = s1;
+    part[3 * blockIdx.x + 2] = 0.0;
   }
 }
 
@@ -167,19 +178,21 @@ __global__ __launch_bounds__(256) void k_pupdate(T *__restrict__ p, const T *__r
     p[s] = fma(beta, p[s], z[s]);
 }
 
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_NORM = 3 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_NORM = 3, FIN_BETA_FLEX = 4 };
 
 // Deterministic final reduction of the block partials and the scalar step.
 __global__ __launch_bounds__(RED_TPB) void k_finalize(const double *__restrict__ part, int nblk,
                                                       CGState *__restrict__ st, int mode, int hidx) {
   __shared__ double sh[RED_TPB / 64];
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    s0 += part[2 * b];
-    s1 += part[2 * b + 1];
+    s0 += part[3 * b];
+    s1 += part[3 * b + 1];
+    s2 += part[3 * b + 2];
   }
   s0 = block_sum(s0, sh);
   s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
   if (threadIdx.x != 0) return;
   if (mode == FIN_INIT) {
     st->rho = s0;
@@ -193,8 +206,11 @@ __global__ __launch_bounds__(RED_TPB) void k_finalize(const double *__restrict__
     } else {
       st->alpha = st->rho / s0;
     }
-  } else if (mode == FIN_BETA) {
-    st->beta = st->rho != 0.0 ? s0 / st->rho : 0.0;
+  } else if (mode == FIN_BETA || mode == FIN_BETA_FLEX) {
+    // Fletcher-Reeves (r+, z+)/(r, z), or Polak-Ribiere (z+, r+ - r)/(r, z)
+    // with r+ - r = -alpha q
+    const double num = mode == FIN_BETA ? s0 : -st->alpha * s2;
+    st->beta = st->rho != 0.0 ? num / st->rho : 0.0;
     st->rho = s0;
     st->rr = s1;
     st->hist[hidx] = s1;
@@ -358,16 +374,36 @@ __global__ void k_invert(double *__restrict__ P, const uint8_t *__restrict__ fl,
   }
 }
 
+}  // namespace
+
+// Diagonal 3x3 blocks (xx yy zz xy xz yz, [6][n]) of the operator at every
+// slot, summed over the copies of interface nodes; zero at Dirichlet slots.
+int diag_blocks(hhg_ctx *h, const double *k, int method, double *D, hipStream_t st) {
+  int maxn = 0;
+  for (auto &mi : h->minfo) maxn = std::max(maxn, (int)macro_nodes(mi.n));
+  const int64_t N = h->n_nodes;
+  hipLaunchKernelGGL(k_diag, dim3((maxn + 255) / 256, h->n_macro), dim3(256), 0, st, h->d_minfo,
+                     h->d_sc64, h->d_ec64, k, method, N, D);
+  if (h->n_grp > 0)
+    hipLaunchKernelGGL(k_group_sum6, dim3((unsigned)((6 * h->n_grp + 255) / 256)), dim3(256), 0, st,
+                       h->d_grp_ptr, h->d_grp_slot, h->n_grp, D, N);
+  HHG_HIP(hipGetLastError());
+  return HHG_OK;
+}
+
+namespace {
+
 // ------------------------------------------------------------ workspace
 struct Layout {
   size_t off_r64, off_z64, off_p64, off_q64, off_P64, off_part, off_state;
+  size_t off_feat, off_mlp;
   size_t off_k32, off_b32, off_e32, off_r32, off_z32, off_p32, off_q32, off_P32;
   size_t total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout layout_for(int64_t N, int solver) {
+Layout layout_for(int64_t N, int solver, int precond) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -378,9 +414,13 @@ Layout layout_for(int64_t N, int solver) {
   const size_t v64 = 3 * (size_t)N * 8, v32 = 3 * (size_t)N * 4;
   L.off_r64 = take(v64);
   L.off_P64 = take(6 * (size_t)N * 8);
-  L.off_part = take(2 * RED_GRID * 8);
+  L.off_part = take(3 * RED_GRID * 8);
   L.off_state = take(sizeof(CGState));
-  if (solver == HHG_CG_F64) {
+  if (precond == HHG_PRECOND_LEARNED) {
+    L.off_feat = take(16 * (size_t)N * 2);   // BF16 features
+    L.off_mlp = take(9 * (size_t)N * 4);     // network outputs
+  }
+  if (solver != HHG_IR_F32) {
     L.off_z64 = take(v64);
     L.off_p64 = take(v64);
     L.off_q64 = take(v64);
@@ -410,8 +450,8 @@ struct Host {
 // One preconditioned CG run on A x = b (type T) from the given x to
 // ||r|| <= tol_abs.  Returns HHG_OK / HHG_ENOCONV / HHG_EBREAKDOWN.
 template <typename T>
-int pcg(hhg_ctx *h, int method, const T *b, const T *k, T *x, T *r, T *z, T *p, T *q, const T *P,
-        double *part, CGState *dst, CGState *hst, double tol_abs, int maxit, int check,
+int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T *z, T *p, T *q,
+        const T *P, double *part, CGState *dst, CGState *hst, double tol_abs, int maxit, int check,
         hipStream_t st, int &iters) {
   const int prec = sizeof(T) == 8 ? HHG_F64 : HHG_F32;
   const int64_t N = h->n_nodes;
@@ -437,9 +477,14 @@ int pcg(hhg_ctx *h, int method, const T *b, const T *k, T *x, T *r, T *z, T *p, 
       hipLaunchKernelGGL(k_dot2<T>, dim3(RED_GRID), dim3(RED_TPB), 0, st, p, q, (const T *)nullptr,
                          (const T *)nullptr, h->d_flags, N, part);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst, FIN_ALPHA, 0);
-      hipLaunchKernelGGL(k_update<T>, dim3(RED_GRID), dim3(RED_TPB), 0, st, x, p, r, q, P, z,
-                         h->d_flags, N, dst, part);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst, FIN_BETA, it);
+      if (flex)
+        hipLaunchKernelGGL((k_update<T, true>), dim3(RED_GRID), dim3(RED_TPB), 0, st, x, p, r, q, P, z,
+                           h->d_flags, N, dst, part);
+      else
+        hipLaunchKernelGGL((k_update<T, false>), dim3(RED_GRID), dim3(RED_TPB), 0, st, x, p, r, q, P,
+                           z, h->d_flags, N, dst, part);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst,
+                         flex ? FIN_BETA_FLEX : FIN_BETA, it);
       hipLaunchKernelGGL(k_pupdate<T>, grid_for(3 * N), dim3(256), 0, st, p, z, 3 * N, dst);
     }
     HHG_HIP(hipGetLastError());
@@ -520,9 +565,13 @@ int dot_host(hhg_ctx *h, const double *a, const double *b, double *part, CGState
 
 int check_opts(hhg_ctx *h, const hhg_solve_opts *o) {
   if (!h || !o) return fail(HHG_EINVAL, "null argument");
-  if (o->solver != HHG_CG_F64 && o->solver != HHG_IR_F32) return fail(HHG_EINVAL, "unknown solver");
-  if (o->precond != HHG_PRECOND_NONE && o->precond != HHG_PRECOND_BLOCK_JACOBI)
+  if (o->solver != HHG_CG_F64 && o->solver != HHG_IR_F32 && o->solver != HHG_FCG_F64)
+    return fail(HHG_EINVAL, "unknown solver");
+  if (o->precond != HHG_PRECOND_NONE && o->precond != HHG_PRECOND_BLOCK_JACOBI &&
+      o->precond != HHG_PRECOND_LEARNED)
     return fail(HHG_EINVAL, "unknown preconditioner");
+  if (o->precond == HHG_PRECOND_LEARNED && !h->model)
+    return fail(HHG_EINVAL, "learned preconditioner requested but no model is attached");
   if (o->method != HHG_METHOD_SCALED && o->method != HHG_METHOD_ONTHEFLY)
     return fail(HHG_EINVAL, "unknown operator method");
   if (!(o->rtol > 0.0) || o->maxit < 1) return fail(HHG_EINVAL, "rtol must be > 0 and maxit >= 1");
@@ -563,7 +612,7 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
   std::memset(info, 0, sizeof(*info));
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t N = h->n_nodes;
-  const Layout L = layout_for(N, o->solver);
+  const Layout L = layout_for(N, o->solver, o->precond);
   const int check = std::max(1, std::min(o->check_every > 0 ? o->check_every : 8, MAX_CHECK));
   if (!h->h_state) HHG_HIP(hipHostMalloc((void **)&h->h_state, sizeof(CGState), hipHostMallocDefault));
   CGState *hst = static_cast<CGState *>(h->h_state);
@@ -572,17 +621,16 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
   double *r64 = at<double>(ws, L.off_r64);
   double *P64 = at<double>(ws, L.off_P64);
 
-  // block-Jacobi preconditioner from the operator's diagonal blocks
+  // block-Jacobi preconditioner from the operator's diagonal blocks; the
+  // learned one reshapes it by the network's 3x3 blocks
   {
-    int maxn = 0;
-    for (auto &mi : h->minfo) maxn = std::max(maxn, (int)macro_nodes(mi.n));
-    hipLaunchKernelGGL(k_diag, dim3((maxn + 255) / 256, h->n_macro), dim3(256), 0, st, h->d_minfo,
-                       h->d_sc64, h->d_ec64, k, o->method, N, P64);
-    if (h->n_grp > 0)
-      hipLaunchKernelGGL(k_group_sum6, dim3((unsigned)((6 * h->n_grp + 255) / 256)), dim3(256), 0, st,
-                         h->d_grp_ptr, h->d_grp_slot, h->n_grp, P64, N);
+    if ((rc = diag_blocks(h, k, o->method, P64, st))) return rc;
     hipLaunchKernelGGL(k_invert, grid_for(N), dim3(256), 0, st, P64, h->d_flags, N,
                        o->precond == HHG_PRECOND_NONE ? 1 : 0);
+    HHG_HIP(hipGetLastError());
+    if (o->precond == HHG_PRECOND_LEARNED &&
+        (rc = learned_precond(h, k, P64, at<uint16_t>(ws, L.off_feat), at<float>(ws, L.off_mlp), st)))
+      return rc;
     hipLaunchKernelGGL(k_zero_dirichlet<double>, grid_for(N), dim3(256), 0, st, x, h->d_flags, N);
     HHG_HIP(hipGetLastError());
   }
@@ -599,14 +647,14 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
     return HHG_OK;
   }
 
-  if (o->solver == HHG_CG_F64) {
+  if (o->solver != HHG_IR_F32) {
     double *z = at<double>(ws, L.off_z64), *p = at<double>(ws, L.off_p64), *q = at<double>(ws, L.off_q64);
     int outer = 0;
     status = HHG_ENOCONV;
     while (total < o->maxit) {
       int it = 0;
       ++outer;
-      rc = pcg<double>(h, o->method, b, k, x, r64, z, p, q, P64, part, dst, hst, o->rtol * bnorm,
+      rc = pcg<double>(h, o->method, o->solver == HHG_FCG_F64, b, k, x, r64, z, p, q, P64, part, dst, hst, o->rtol * bnorm,
                        o->maxit - total, check, st, it);
       total += it;
       if (rc == HHG_EBREAKDOWN || (rc != HHG_OK && rc != HHG_ENOCONV)) {
@@ -654,7 +702,7 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
       hipLaunchKernelGGL(k_fill<float>, grid_for(3 * N), dim3(256), 0, st, e32, 0.0f, 3 * N);
       HHG_HIP(hipGetLastError());
       int it = 0;
-      rc = pcg<float>(h, o->method, b32, k32, e32, r32, z32, p32, q32, P32, part, dst, hst,
+      rc = pcg<float>(h, o->method, false, b32, k32, e32, r32, z32, p32, q32, P32, part, dst, hst,
                       o->inner_rtol * std::sqrt(rr), o->maxit - total, check, st, it);
       total += it;
       if (rc == HHG_EBREAKDOWN || (rc != HHG_OK && rc != HHG_ENOCONV)) {
@@ -675,7 +723,9 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
 }
 }  // namespace
 
-size_t workspace_bytes(hhg_ctx *h, int solver) { return layout_for(h->n_nodes, solver).total; }
+size_t workspace_bytes(hhg_ctx *h, int solver, int precond) {
+  return layout_for(h->n_nodes, solver, precond).total;
+}
 
 }  // namespace hhg
 
@@ -683,14 +733,51 @@ extern "C" {
 
 int hhg_workspace_bytes(hhg_handle h, const hhg_solve_opts *o, size_t *bytes) {
   if (!h || !o || !bytes) return hhg::fail(HHG_EINVAL, "null argument");
-  if (o->solver != HHG_CG_F64 && o->solver != HHG_IR_F32) return hhg::fail(HHG_EINVAL, "unknown solver");
-  *bytes = hhg::workspace_bytes(h, o->solver);
+  if (o->solver != HHG_CG_F64 && o->solver != HHG_IR_F32 && o->solver != HHG_FCG_F64)
+    return hhg::fail(HHG_EINVAL, "unknown solver");
+  *bytes = hhg::workspace_bytes(h, o->solver, o->precond);
   return HHG_OK;
 }
 
 int hhg_cg_solve(hhg_handle h, const hhg_solve_opts *o, const double *b, const double *k,
                  double *x, void *workspace, hhg_solve_info *info, void *stream) {
   return hhg::solve_entry(h, o, b, k, x, workspace, info, (hipStream_t)stream);
+}
+
+int hhg_preconditioner(hhg_handle h, int32_t precond, int32_t method, const double *k, double *P,
+                       void *stream) {
+  using namespace hhg;
+  if (!h || !k || !P) return fail(HHG_EINVAL, "null argument");
+  if (((uintptr_t)k | (uintptr_t)P) & 7) return fail(HHG_EINVAL, "misaligned pointer");
+  if (precond != HHG_PRECOND_NONE && precond != HHG_PRECOND_BLOCK_JACOBI &&
+      precond != HHG_PRECOND_LEARNED)
+    return fail(HHG_EINVAL, "unknown preconditioner");
+  if (method != HHG_METHOD_SCALED && method != HHG_METHOD_ONTHEFLY)
+    return fail(HHG_EINVAL, "unknown operator method");
+  if (precond == HHG_PRECOND_LEARNED && !h->model)
+    return fail(HHG_EINVAL, "learned preconditioner requested but no model is attached");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = h->n_nodes;
+  if ((rc = diag_blocks(h, k, method, P, st))) return rc;
+  hipLaunchKernelGGL(k_invert, grid_for(N), dim3(256), 0, st, P, h->d_flags, N,
+                     precond == HHG_PRECOND_NONE ? 1 : 0);
+  HHG_HIP(hipGetLastError());
+  if (precond == HHG_PRECOND_LEARNED) {
+    void *scratch = nullptr;
+    const size_t fb = ((16 * (size_t)N * 2 + 255) / 256) * 256;
+    HHG_HIP(hipMalloc(&scratch, fb + 9 * (size_t)N * 4));
+    rc = learned_precond(h, k, P, static_cast<uint16_t *>(scratch),
+                         reinterpret_cast<float *>(static_cast<char *>(scratch) + fb), st);
+    hipError_t se = hipStreamSynchronize(st);
+    (void)hipFree(scratch);
+    if (rc) return rc;
+    if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+    return HHG_OK;
+  }
+  HHG_HIP(hipStreamSynchronize(st));
+  return HHG_OK;
 }
 
 }  // extern "C"

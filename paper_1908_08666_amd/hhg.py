@@ -131,8 +131,9 @@ class Mesh:
     # ------------------------------------------------------------ solvers
     def solve_opts(self, solver="cg64", precond="block_jacobi", method="scaled", rtol=1e-8,
                    maxit=20000, inner_rtol=1e-3, check_every=8):
-        return L.SolveOpts({"cg64": L.HHG_CG_F64, "ir32": L.HHG_IR_F32}[solver],
-                           {"none": L.HHG_PRECOND_NONE, "block_jacobi": L.HHG_PRECOND_BLOCK_JACOBI}[precond],
+        return L.SolveOpts({"cg64": L.HHG_CG_F64, "ir32": L.HHG_IR_F32, "fcg64": L.HHG_FCG_F64}[solver],
+                           {"none": L.HHG_PRECOND_NONE, "block_jacobi": L.HHG_PRECOND_BLOCK_JACOBI,
+                            "learned": L.HHG_PRECOND_LEARNED}[precond],
                            {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method],
                            int(maxit), float(rtol), float(inner_rtol), int(check_every), 0)
 

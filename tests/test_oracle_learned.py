@@ -105,7 +105,7 @@ def test_zero_head_is_block_jacobi_and_sample_loss():
     BJ = S.block_jacobi_inverse(Auu).toarray()
     Pm = LN.block_matrix(P, mesh.unknown).toarray()
     assert np.allclose(Pm, BJ, rtol=1e-13, atol=1e-13 * np.abs(BJ).max())
-    # loss of a sample with M = 0 is |D^{-1} r - e|^2 / |D^{-1} r|^2
+    # loss of a sample with M = 0 is |D^{-1} r - e|^2 / (|D^{-1} r|^2 + |e|^2)
     rng = np.random.default_rng(2)
     u = mesh.unknown
     D = LN.diag_blocks(A, u)
@@ -115,7 +115,7 @@ def test_zero_head_is_block_jacobi_and_sample_loss():
     Fs, rs, es, S6 = LN.make_samples(F, r, e, D)
     loss, _ = LN.loss_and_grad(w, Fs, rs, es, S6)
     Dr = np.einsum("nab,nb->na", np.linalg.inv(D), r)
-    want = np.mean(np.sum((Dr - e) ** 2, 1) / np.sum(Dr ** 2, 1))
+    want = np.mean(np.sum((Dr - e) ** 2, 1) / (np.sum(Dr ** 2, 1) + np.sum(e ** 2, 1)))
     assert abs(loss - want) <= 1e-12 * want
 
 

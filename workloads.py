@@ -177,9 +177,41 @@ def velocity_gradient(xyz: np.ndarray, rng: np.random.Generator, scale: float,
     return scale * 2.0 * np.pi * np.einsum('nm,mc,md->ncd', cosv, b, kv)
 
 
+def consistent_uniform(xyz: np.ndarray, owner: np.ndarray, rng: np.random.Generator,
+                       ncomp: int = 3, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """U(lo, hi) values drawn once per distinct node (the slots flagged in
+    ``owner``) and copied to every slot at the same position; (ncomp, n)."""
+    from scipy.spatial import cKDTree
+    owners = np.nonzero(owner)[0]
+    _, idx = cKDTree(xyz[owners]).query(xyz)
+    vals = rng.uniform(lo, hi, size=(ncomp, owners.shape[0]))
+    return np.ascontiguousarray(vals[:, idx])
+
+
 def uniform_vector(n: int, rng: np.random.Generator) -> np.ndarray:
     """Entries U(-1, 1), float64."""
     return rng.uniform(-1.0, 1.0, size=n)
+
+
+def localized_velocity_field(xyz: np.ndarray, rng: np.random.Generator, scale: float,
+                             width: float = 0.12, n_modes: int = 8) -> np.ndarray:
+    """Smooth velocity concentrated around a seeded centre c in the middle of
+    the unit cube: exp(-|x - c|^2 / (2 width^2)) times ``velocity_field``.
+    Its strain rate spans many orders of magnitude across the cube, so the
+    Carreau viscosity sweeps most of the range eta_inf .. eta0; (N, 3)."""
+    c = rng.uniform(0.35, 0.65, size=3)
+    env = np.exp(-np.sum((xyz - c) ** 2, axis=1) / (2.0 * width * width))
+    return env[:, None] * velocity_field(xyz, rng, scale, n_modes)
+
+
+def smoother_init_weights(rng: np.random.Generator) -> np.ndarray:
+    """Initial parameters of the 16-64-9 smoother network as one FP32 vector
+    (W1 [16][64] row-major, b1, W2 [64][9], b2): W1 He-uniform, everything
+    else zero, so the untrained network is block Jacobi."""
+    lim = np.sqrt(6.0 / 16.0)
+    w = np.zeros(16 * 64 + 64 + 64 * 9 + 9, dtype=np.float32)
+    w[:16 * 64] = rng.uniform(-lim, lim, size=16 * 64).astype(np.float32)
+    return w
 
 
 # ------------------------------------------------------- material constants
