@@ -18,19 +18,17 @@ __device__ __forceinline__ int plane_base32(int n, int k) {
   return a * (a + 1) * (a + 2) / 6 - b * (b + 1) * (b + 2) / 6;
 }
 
-template <typename T, bool RESID, bool ROWWISE, bool CORR>
-__global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
-    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
-    const ElemConst<T> *__restrict__ ecs, const int32_t *__restrict__ bijk,
-    const int32_t *__restrict__ bblk, const uint8_t *__restrict__ flags,
-    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn) {
-  const int m = bblk[blockIdx.x];
-  const int packed = bijk[(int64_t)blockIdx.x * BOUNDARY_BLOCK + threadIdx.x];
-  if (packed < 0) return;
-  const MacroInfo mi = minfo[m];
+// One macro-boundary row of macro m at (i, j, k): the neighbours' positions
+// are classified at run time (inside the macro, on its boundary) and
+// Dirichlet values of x are masked.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+__device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilConst<T> &sc,
+                                             const ElemConst<T> &ec, int i, int j, int k,
+                                             const uint8_t *__restrict__ flags,
+                                             const T *__restrict__ x, const T *__restrict__ kc,
+                                             const T *__restrict__ f, T *__restrict__ y,
+                                             int64_t nn) {
   const int n = mi.n;
-  const int i = packed & 1023, j = (packed >> 10) & 1023, k = (packed >> 20) & 1023;
   const T *X0 = x + mi.off;
   const T *X1 = X0 + nn;
   const T *X2 = X1 + nn;
@@ -60,13 +58,14 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
   }
   const T ci0 = X0[lslot], ci1 = X1[lslot], ci2 = X2[lslot];
   const T ck = KC[lslot];
-  const ElemConst<T> &ec = ecs[m];
   T y0 = T(0), y1 = T(0), y2 = T(0);
 #pragma unroll
   for (int t = 0; t < NTET; ++t) {
     const int v1 = TET_V[t][0], v2 = TET_V[t][1], v3 = TET_V[t][2];
     if (!(in[v1] && in[v2] && in[v3])) continue;
     const T kb = T(0.25) * (ck + nk[v1] + nk[v2] + nk[v3]);
+    // this element's part of the row: kb (B1 x) + B0 x over its vertices
+    T u0 = T(0), u1 = T(0), u2 = T(0), q0 = T(0), q1 = T(0), q2 = T(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       T d0, d1, d2;
@@ -78,14 +77,21 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
         d0 = nx0[v]; d1 = nx1[v]; d2 = nx2[v];
       }
       const T *B1 = ec.b1[t][c];
-      const T *B0 = ec.b0[t][c];
-      y0 += fma(kb, B1[0], B0[0]) * d0 + fma(kb, B1[1], B0[1]) * d1 + fma(kb, B1[2], B0[2]) * d2;
-      y1 += fma(kb, B1[3], B0[3]) * d0 + fma(kb, B1[4], B0[4]) * d1 + fma(kb, B1[5], B0[5]) * d2;
-      y2 += fma(kb, B1[6], B0[6]) * d0 + fma(kb, B1[7], B0[7]) * d1 + fma(kb, B1[8], B0[8]) * d2;
+      u0 = fma(B1[0], d0, fma(B1[1], d1, fma(B1[2], d2, u0)));
+      u1 = fma(B1[3], d0, fma(B1[4], d1, fma(B1[5], d2, u1)));
+      u2 = fma(B1[6], d0, fma(B1[7], d1, fma(B1[8], d2, u2)));
+      if constexpr (A0) {
+        const T *B0 = ec.b0[t][c];
+        q0 = fma(B0[0], d0, fma(B0[1], d1, fma(B0[2], d2, q0)));
+        q1 = fma(B0[3], d0, fma(B0[4], d1, fma(B0[5], d2, q1)));
+        q2 = fma(B0[6], d0, fma(B0[7], d1, fma(B0[8], d2, q2)));
+      }
     }
+    y0 = fma(kb, u0, y0 + q0);
+    y1 = fma(kb, u1, y1 + q1);
+    y2 = fma(kb, u2, y2 + q2);
   }
   if (!ROWWISE) {
-    const StencilConst<T> &sc = scs[m];
 #pragma unroll
     for (int d = 0; d < NDIR; ++d) {
       if (!in[d] || onb[d]) continue;
@@ -96,10 +102,9 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
       const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
       const T kh = fma(sc.w_end, ck + nk[d], wr * ring);
       const T *S = sc.shat[d >> 1];
-      const T *A = sc.a0[d >> 1];
       const T z0v = kh * nx0[d], z1v = kh * nx1[d], z2v = kh * nx2[d];
       sym_mv_acc(S, z0v, z1v, z2v, y0, y1, y2);
-      sym_mv_acc(A, nx0[d], nx1[d], nx2[d], y0, y1, y2);
+      if constexpr (A0) sym_mv_acc(sc.a0[d >> 1], nx0[d], nx1[d], nx2[d], y0, y1, y2);
       if (CORR) {
         T w0 = T(0), w1 = T(0), w2 = T(0);
 #pragma unroll
@@ -124,27 +129,68 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
   y[slot + 2 * nn] = y2;
 }
 
+// Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
+// computes the partial row of its macro; copies are summed afterwards.
+// ROWWISE: nodal integration for the whole row (also the on-the-fly method);
+// otherwise scaled entries towards macro-interior neighbours and nodal
+// entries towards macro-boundary neighbours and on the diagonal.  Every block
+// holds nodes of one macro (bblk), ordered by the boundary primitive they lie
+// on, so that a wave rarely diverges; Dirichlet slots of the macro's boundary
+// (flag bit 30 in bijk) get their zero rows here as well.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+__global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
+    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
+    const ElemConst<T> *__restrict__ ecs, const int32_t *__restrict__ bijk,
+    const int32_t *__restrict__ bblk, const uint8_t *__restrict__ flags,
+    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
+    T *__restrict__ y, int64_t nn) {
+  // the macro's constants are staged in LDS and read from there by every
+  // row (scalar loads of 15 KB of constants would not fit the scalar
+  // registers); all lanes read the same address, so the reads broadcast
+  __shared__ __align__(16) unsigned char cbuf[sizeof(ElemConst<T>) + sizeof(StencilConst<T>)];
+  const int m = bblk[blockIdx.x];
+  {
+    static_assert(sizeof(ElemConst<T>) % 16 == 0 && sizeof(StencilConst<T>) % 4 == 0, "table sizes");
+    const uint4 *ge = reinterpret_cast<const uint4 *>(ecs + m);
+    const uint32_t *gs = reinterpret_cast<const uint32_t *>(scs + m);
+    uint4 *le = reinterpret_cast<uint4 *>(cbuf);
+    uint32_t *ls = reinterpret_cast<uint32_t *>(cbuf + sizeof(ElemConst<T>));
+    for (int q = threadIdx.x; q < (int)(sizeof(ElemConst<T>) / 16); q += BOUNDARY_BLOCK) le[q] = ge[q];
+    for (int q = threadIdx.x; q < (int)(sizeof(StencilConst<T>) / 4); q += BOUNDARY_BLOCK) ls[q] = gs[q];
+  }
+  __syncthreads();
+  const int packed = bijk[(int64_t)blockIdx.x * BOUNDARY_BLOCK + threadIdx.x];
+  if (packed < 0) return;
+  const MacroInfo mi = minfo[m];
+  const int i = packed & 1023, j = (packed >> 10) & 1023, k = (packed >> 20) & 1023;
+  const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(cbuf);
+  const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(cbuf + sizeof(ElemConst<T>));
+  if (packed & (1 << 30)) {                // Dirichlet slot: its row is zero
+    const int64_t slot = mi.off + plane_base32(mi.n, k) + (i + j) * (i + j + 1) / 2 + i;
+    y[slot] = T(0);
+    y[slot + nn] = T(0);
+    y[slot + 2 * nn] = T(0);
+    return;
+  }
+  boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, flags, x, kc, f, y, nn);
+}
+
 // Sum of the partial rows of all copies of an interface node; the total (or
 // f minus it) is written to every copy, keeping the output consistent.
-// Threads past the groups write the zero rows of the Dirichlet slots.
 template <typename T, bool RESID>
 __global__ __launch_bounds__(256) void k_finish(const int64_t *__restrict__ ptr,
                                                 const int64_t *__restrict__ slots, int64_t ng,
-                                                const int64_t *__restrict__ dslot, int64_t nd,
                                                 const T *__restrict__ f, T *__restrict__ y,
                                                 int64_t nn) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (item, component)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (group, component)
   const int64_t g = t / 3;
   const int c = (int)(t - 3 * g);
-  if (g < ng) {
-    const int64_t a = ptr[g], b = ptr[g + 1];
-    T sum = T(0);
-    for (int64_t q = a; q < b; ++q) sum += y[c * nn + slots[q]];
-    if (RESID) sum = f[c * nn + slots[a]] - sum;
-    for (int64_t q = a; q < b; ++q) y[c * nn + slots[q]] = sum;
-  } else if (g - ng < nd) {
-    y[c * nn + dslot[g - ng]] = T(0);
-  }
+  if (g >= ng) return;
+  const int64_t a = ptr[g], b = ptr[g + 1];
+  T sum = T(0);
+  for (int64_t q = a; q < b; ++q) sum += y[c * nn + slots[q]];
+  if (RESID) sum = f[c * nn + slots[a]] - sum;
+  for (int64_t q = a; q < b; ++q) y[c * nn + slots[q]] = sum;
 }
 
 // ------------------------------------------------------------ launchers
@@ -157,27 +203,28 @@ int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, 
   const bool corr = h->op.corr == HHG_CORR_PHYSICAL;
   if (!h->bblk.empty()) {
     const dim3 grid((unsigned)h->bblk.size());
-#define HHG_LB(RW, CR)                                                                           \
-  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR>), grid, dim3(BOUNDARY_BLOCK), 0, st,    \
+#define HHG_LB(RW, CR, A0)                                                                       \
+  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR, A0>), grid, dim3(BOUNDARY_BLOCK), 0, st, \
                      h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_bijk, h->d_bblk, h->d_flags, x, \
                      k, f, y, h->n_nodes)
     ProfScope prof(h, HHG_K_BOUNDARY_ROWS, st);
-    if (rowwise)
-      HHG_LB(true, false);
-    else if (corr)
-      HHG_LB(false, true);
-    else
-      HHG_LB(false, false);
+    const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
+    if (rowwise) {
+      if (a0) HHG_LB(true, false, true); else HHG_LB(true, false, false);
+    } else if (corr) {
+      if (a0) HHG_LB(false, true, true); else HHG_LB(false, true, false);
+    } else {
+      if (a0) HHG_LB(false, false, true); else HHG_LB(false, false, false);
+    }
 #undef HHG_LB
     HHG_HIP(hipGetLastError());
   }
-  const int64_t nd = (int64_t)h->dslot.size();
-  const int64_t total = 3 * (h->n_grp + nd);
+  const int64_t total = 3 * h->n_grp;
   if (total > 0) {
     const dim3 g2((unsigned)((total + 255) / 256));
     ProfScope prof(h, HHG_K_GROUP_SUM, st);
     hipLaunchKernelGGL((k_finish<T, RESID>), g2, dim3(256), 0, st, h->d_grp_ptr, h->d_grp_slot,
-                       h->n_grp, h->d_dslot, nd, f, y, h->n_nodes);
+                       h->n_grp, f, y, h->n_nodes);
     HHG_HIP(hipGetLastError());
   }
   return HHG_OK;
@@ -198,17 +245,21 @@ int apply_t(hhg_ctx *h, int method, const T *f, const T *x, const T *k, T *y, hi
     return f ? launch_boundary<T, true>(h, method, x, k, f, y, st)
              : launch_boundary<T, false>(h, method, x, k, f, y, st);
   }
+  // the small boundary launch goes first: queued behind the interior launch,
+  // which fills every compute unit, it would only start as that one drains
   HHG_HIP(hipEventRecord(h->ev_fork, st));
   HHG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
   int rc;
   if (f) {
-    rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, true>(h, x, k, f, y, st)
-                                 : launch_interior_v<T, METHOD_ONTHEFLY, true>(h, x, k, f, y, st);
-    if (!rc) rc = launch_boundary<T, true>(h, method, x, k, f, y, h->side);
+    rc = launch_boundary<T, true>(h, method, x, k, f, y, h->side);
+    if (!rc)
+      rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, true>(h, x, k, f, y, st)
+                                   : launch_interior_v<T, METHOD_ONTHEFLY, true>(h, x, k, f, y, st);
   } else {
-    rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, st)
-                                 : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, st);
-    if (!rc) rc = launch_boundary<T, false>(h, method, x, k, f, y, h->side);
+    rc = launch_boundary<T, false>(h, method, x, k, f, y, h->side);
+    if (!rc)
+      rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, st)
+                                   : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, st);
   }
   HHG_HIP(hipEventRecord(h->ev_join, h->side));
   HHG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));

@@ -138,8 +138,7 @@ __device__ __forceinline__ void interior_item(
   const T *K = kc + mi.off;
 
   // plane kk of the window: global -> registers (Dirichlet values of x zeroed)
-  Node4<T> pre[NW];
-  auto fetch = [&](int kk) {
+  auto fetch = [&](int kk, Node4<T>(&dst)[NW]) {
     const int ps = (int)tri(n + 1 - kk);
     const int64_t base = plane_base(n, kk);
 #pragma unroll
@@ -157,38 +156,55 @@ __device__ __forceinline__ void interior_item(
         const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
         if ((mi.dmask >> z) & 1u) v.x0 = v.x1 = v.x2 = T(0);
       }
-      pre[r] = v;
+      dst[r] = v;
     }
   };
   // registers -> LDS slot of plane kk
-  auto put = [&](int kk) {
+  auto put = [&](int kk, const Node4<T>(&src)[NW]) {
     Pair<T> *da = bufA + (kk % 3) * wl;
     Pair<T> *db = bufB + (kk % 3) * wl;
 #pragma unroll
     for (int r = 0; r < NW; ++r) {
       const int e = tid + r * TPB;
       if (e < wl) {
-        da[e] = Pair<T>{pre[r].x0, pre[r].x1};
-        db[e] = Pair<T>{pre[r].x2, pre[r].k};
+        da[e] = Pair<T>{src[r].x0, src[r].x1};
+        db[e] = Pair<T>{src[r].x2, src[r].k};
       }
     }
   };
 
-  fetch(w.ka - 1);
-  put(w.ka - 1);
-  fetch(w.ka);
-  put(w.ka);
-  fetch(w.ka + 1);
-  put(w.ka + 1);
+  Node4<T> pre[NW];
+  {
+    // the first three planes in one round of loads
+    Node4<T> pa[NW], pb[NW];
+    fetch(w.ka - 1, pa);
+    fetch(w.ka, pb);
+    fetch(w.ka + 1, pre);
+    put(w.ka - 1, pa);
+    put(w.ka, pb);
+    put(w.ka + 1, pre);
+  }
   __syncthreads();
   const int e0 = p - ws;
   const bool col_ok = (s >= 2) && (i >= 1) && (j >= 1);
 
+  // Per plane: loads of plane kk+2 are issued first and land while plane kk
+  // computes; the results of plane kk are stored only after plane kk+2 has
+  // been written to LDS, so that waiting for those loads never waits for
+  // stores issued a moment earlier (both share one counter).
   for (int kk = w.ka; kk < w.kb; ++kk) {
-    // the plane needed by the next step is loaded while this one computes
     const bool more = kk + 2 <= w.kb;
-    if (more) fetch(kk + 2);
-    if (col_ok && s + kk <= n - 1) {
+    if (more) fetch(kk + 2, pre);
+    const bool act = col_ok && s + kk <= n - 1;
+    const int64_t g = mi.off + plane_base(n, kk) + p;
+    T y0 = T(0), y1 = T(0), y2 = T(0);
+    if (act) {
+      T f0 = T(0), f1 = T(0), f2 = T(0);
+      if constexpr (RESID) {
+        f0 = f[g];
+        f1 = f[g + nn];
+        f2 = f[g + 2 * nn];
+      }
       const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
       const int o0 = (kk % 3) * wl + e0;
       const int op = ((kk + 1) % 3) * wl + e0;
@@ -208,20 +224,20 @@ __device__ __forceinline__ void interior_item(
       __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
       __builtin_amdgcn_sched_barrier(0);
-      T y0, y1, y2;
       node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
-      const int64_t g = mi.off + plane_base(n, kk) + p;
       if constexpr (RESID) {
-        y0 = f[g] - y0;
-        y1 = f[g + nn] - y1;
-        y2 = f[g + 2 * nn] - y2;
+        y0 = f0 - y0;
+        y1 = f1 - y1;
+        y2 = f2 - y2;
       }
+    }
+    __syncthreads();
+    if (more) put(kk + 2, pre);          // overwrites the slot of plane kk-1
+    if (act) {
       y[g] = y0;
       y[g + nn] = y1;
       y[g + 2 * nn] = y2;
     }
-    __syncthreads();
-    if (more) put(kk + 2);               // overwrites the slot of plane kk-1
     __syncthreads();
   }
 }

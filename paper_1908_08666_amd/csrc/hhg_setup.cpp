@@ -592,17 +592,30 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
     size_t q = 0;
     for (int m = 0; m < M; ++m) {
       size_t cnt = 0;
+      // rows of one boundary primitive (face, edge, vertex) together, so that
+      // the waves of the boundary-row kernel rarely diverge; then the
+      // macro's Dirichlet slots (bit 30), whose rows the kernel sets to zero
+      std::vector<std::pair<int, int32_t>> rows;
+      std::vector<int32_t> drows;
+      const int n = h->minfo[m].n;
       for (; q < bslot.size() && bslot[q].x == m; ++q) {
-        const int n = h->minfo[m].n;
         const int i = bslot[q].y & 1023, j = (bslot[q].y >> 10) & 1023, k = (bslot[q].y >> 20) & 1023;
         const int64_t slot = h->minfo[m].off + plane_base(n, k) + tri(i + j) + i;
         if (h->flags[slot] & 1) {
           dslot.push_back(slot);
+          drows.push_back(bslot[q].y | (1 << 30));
           continue;
         }
-        bijk.push_back(bslot[q].y);
-        ++cnt;
+        const int z = ((n - i - j - k) == 0) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3);
+        rows.push_back({z, bslot[q].y});
       }
+      std::stable_sort(rows.begin(), rows.end(),
+                       [](const std::pair<int, int32_t> &a, const std::pair<int, int32_t> &b) {
+                         return a.first < b.first;
+                       });
+      for (auto &r : rows) bijk.push_back(r.second);
+      for (int32_t v : drows) bijk.push_back(v);
+      cnt = rows.size() + drows.size();
       const size_t pad = (BOUNDARY_BLOCK - cnt % BOUNDARY_BLOCK) % BOUNDARY_BLOCK;
       for (size_t r = 0; r < pad; ++r) bijk.push_back(-1);
       for (size_t r = 0; r < (cnt + pad) / BOUNDARY_BLOCK; ++r) bblk.push_back(m);
