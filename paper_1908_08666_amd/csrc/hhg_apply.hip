@@ -176,21 +176,35 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
 }
 
 // Sum of the partial rows of all copies of an interface node; the total (or
-// f minus it) is written to every copy, keeping the output consistent.
+// f minus it) is written to every copy, keeping the output consistent.  One
+// thread per group handles the three components (the copy list is read once).
 template <typename T, bool RESID>
 __global__ __launch_bounds__(256) void k_finish(const int64_t *__restrict__ ptr,
                                                 const int64_t *__restrict__ slots, int64_t ng,
                                                 const T *__restrict__ f, T *__restrict__ y,
                                                 int64_t nn) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (group, component)
-  const int64_t g = t / 3;
-  const int c = (int)(t - 3 * g);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ng) return;
   const int64_t a = ptr[g], b = ptr[g + 1];
-  T sum = T(0);
-  for (int64_t q = a; q < b; ++q) sum += y[c * nn + slots[q]];
-  if (RESID) sum = f[c * nn + slots[a]] - sum;
-  for (int64_t q = a; q < b; ++q) y[c * nn + slots[q]] = sum;
+  T s0 = T(0), s1 = T(0), s2 = T(0);
+  for (int64_t q = a; q < b; ++q) {
+    const int64_t sl = slots[q];
+    s0 += y[sl];
+    s1 += y[nn + sl];
+    s2 += y[2 * nn + sl];
+  }
+  if (RESID) {
+    const int64_t s = slots[a];
+    s0 = f[s] - s0;
+    s1 = f[nn + s] - s1;
+    s2 = f[2 * nn + s] - s2;
+  }
+  for (int64_t q = a; q < b; ++q) {
+    const int64_t sl = slots[q];
+    y[sl] = s0;
+    y[nn + sl] = s1;
+    y[2 * nn + sl] = s2;
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -219,7 +233,7 @@ int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, 
 #undef HHG_LB
     HHG_HIP(hipGetLastError());
   }
-  const int64_t total = 3 * h->n_grp;
+  const int64_t total = h->n_grp;
   if (total > 0) {
     const dim3 g2((unsigned)((total + 255) / 256));
     ProfScope prof(h, HHG_K_GROUP_SUM, st);

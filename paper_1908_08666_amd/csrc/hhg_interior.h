@@ -100,9 +100,10 @@ __device__ __forceinline__ void node_rows(const Node4<T> &c, const Node4<T> (&nb
   }
 }
 
-// One work item (a slab of TPB positions over planes [ka, kb) of one macro)
-// computed by the whole workgroup; every thread must call it (barriers).
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+// One work item (a slab of NSUB * TPB positions over planes [ka, kb) of one
+// macro) computed by the whole workgroup, NSUB positions per thread (p0 + tid
+// + u TPB); every thread must call it (barriers).
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
 __device__ __forceinline__ void interior_item(
     const WorkItem w, unsigned char *smem_raw,
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
@@ -114,11 +115,7 @@ __device__ __forceinline__ void interior_item(
   const MacroInfo mi = minfo[w.macro];
   const int n = mi.n;
   const int tid = threadIdx.x;
-  const int p0 = w.chunk * TPB;
-  const int p = p0 + tid;
-  const int s = tri_root_dev(p);
-  const int i = p - s * (s + 1) / 2;
-  const int j = s - i;
+  const int p0 = w.chunk * (TPB * NSUB);
   const int s_lo = tri_root_dev(p0);
   const int ws = max(0, p0 - s_lo - 1);
 
@@ -185,8 +182,18 @@ __device__ __forceinline__ void interior_item(
     put(w.ka + 1, pre);
   }
   __syncthreads();
-  const int e0 = p - ws;
-  const bool col_ok = (s >= 2) && (i >= 1) && (j >= 1);
+  // the positions of this thread: anti-diagonal, interior column
+  int ps_[NSUB], ss_[NSUB];
+  bool col_ok[NSUB];
+#pragma unroll
+  for (int u = 0; u < NSUB; ++u) {
+    const int p = p0 + tid + u * TPB;
+    const int sp = tri_root_dev(p);
+    const int ip = p - sp * (sp + 1) / 2;
+    ps_[u] = p;
+    ss_[u] = sp;
+    col_ok[u] = (sp >= 2) && (ip >= 1) && (sp - ip >= 1);
+  }
 
   // Per plane: loads of plane kk+2 are issued first and land while plane kk
   // computes; the results of plane kk are stored only after plane kk+2 has
@@ -195,55 +202,70 @@ __device__ __forceinline__ void interior_item(
   for (int kk = w.ka; kk < w.kb; ++kk) {
     const bool more = kk + 2 <= w.kb;
     if (more) fetch(kk + 2, pre);
-    const bool act = col_ok && s + kk <= n - 1;
-    const int64_t g = mi.off + plane_base(n, kk) + p;
-    T y0 = T(0), y1 = T(0), y2 = T(0);
-    if (act) {
-      T f0 = T(0), f1 = T(0), f2 = T(0);
-      if constexpr (RESID) {
-        f0 = f[g];
-        f1 = f[g + nn];
-        f2 = f[g + 2 * nn];
-      }
-      const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
-      const int o0 = (kk % 3) * wl + e0;
-      const int op = ((kk + 1) % 3) * wl + e0;
-      auto rd = [&](int o) {
-        const Pair<T> a = bufA[o], b = bufB[o];
-        return Node4<T>{a.a, a.b, b.a, b.b};
-      };
-      const Node4<T> c = rd(o0);
-      Node4<T> nb[NDIR];
+    const int64_t gk = mi.off + plane_base(n, kk);
+    T yv[NSUB][3];
+    bool act[NSUB];
 #pragma unroll
-      for (int d = 0; d < NDIR; ++d) {
-        const int o = DIR_K[d] > 0 ? op : (DIR_K[d] < 0 ? om : o0);
-        nb[d] = rd(o + dir_a(d) + dir_b(d) * s);
-      }
-      // LDS reads and the scalar loads of the stencil constants share one
-      // wait counter: take all neighbour records before any constant load
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-      __builtin_amdgcn_sched_barrier(0);
-      node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
-      if constexpr (RESID) {
-        y0 = f0 - y0;
-        y1 = f1 - y1;
-        y2 = f2 - y2;
+    for (int u = 0; u < NSUB; ++u) {
+      const int p = ps_[u], sp = ss_[u];
+      act[u] = col_ok[u] && sp + kk <= n - 1;
+      yv[u][0] = yv[u][1] = yv[u][2] = T(0);
+      if (act[u]) {
+        const int64_t g = gk + p;
+        T f0 = T(0), f1 = T(0), f2 = T(0);
+        if constexpr (RESID) {
+          f0 = f[g];
+          f1 = f[g + nn];
+          f2 = f[g + 2 * nn];
+        }
+        const int e0 = p - ws;
+        const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
+        const int o0 = (kk % 3) * wl + e0;
+        const int op = ((kk + 1) % 3) * wl + e0;
+        auto rd = [&](int o) {
+          const Pair<T> a = bufA[o], b = bufB[o];
+          return Node4<T>{a.a, a.b, b.a, b.b};
+        };
+        const Node4<T> c = rd(o0);
+        Node4<T> nb[NDIR];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) {
+          const int o = DIR_K[d] > 0 ? op : (DIR_K[d] < 0 ? om : o0);
+          nb[d] = rd(o + dir_a(d) + dir_b(d) * sp);
+        }
+        // LDS reads and the scalar loads of the stencil constants share one
+        // wait counter: take all neighbour records before any constant load
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        __builtin_amdgcn_sched_barrier(0);
+        T y0, y1, y2;
+        node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
+        if constexpr (RESID) {
+          y0 = f0 - y0;
+          y1 = f1 - y1;
+          y2 = f2 - y2;
+        }
+        yv[u][0] = y0;
+        yv[u][1] = y1;
+        yv[u][2] = y2;
       }
     }
     __syncthreads();
     if (more) put(kk + 2, pre);          // overwrites the slot of plane kk-1
-    if (act) {
-      y[g] = y0;
-      y[g + nn] = y1;
-      y[g + 2 * nn] = y2;
-    }
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u)
+      if (act[u]) {
+        const int64_t g = gk + ps_[u];
+        y[g] = yv[u][0];
+        y[g + nn] = yv[u][1];
+        y[g + 2 * nn] = yv[u][2];
+      }
     __syncthreads();
   }
 }
 
 // One workgroup per work item.
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
 __global__ __launch_bounds__(TPB) void k_interior(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
@@ -252,8 +274,8 @@ __global__ __launch_bounds__(TPB) void k_interior(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const WorkItem w = work[blockIdx.x];
   if (w.macro < 0) return;                  // padding item of the XCD-aware order
-  interior_item<T, METHOD, RESID, CORR, A0, NW, TPB>(w, smem_raw, minfo, scs, ecs, x, kc, f, y,
-                                                     nn, wl);
+  interior_item<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc, f,
+                                                           y, nn, wl);
 }
 
 // Persistent form: a grid of resident workgroups walks the work list with a
@@ -261,7 +283,7 @@ __global__ __launch_bounds__(TPB) void k_interior(
 // that is a multiple of the XCD count every item keeps the XCD that the
 // list's order assigns it.  Every workgroup leaves after at most
 // ceil(n_work / gridDim.x) items.
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
 __global__ __launch_bounds__(TPB) void k_interior_persist(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work, int n_work,
@@ -271,8 +293,8 @@ __global__ __launch_bounds__(TPB) void k_interior_persist(
   for (int q = blockIdx.x; q < n_work; q += gridDim.x) {
     const WorkItem w = work[q];
     if (w.macro >= 0)                       // block-uniform
-      interior_item<T, METHOD, RESID, CORR, A0, NW, TPB>(w, smem_raw, minfo, scs, ecs, x, kc, f,
-                                                         y, nn, wl);
+      interior_item<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc,
+                                                               f, y, nn, wl);
     __syncthreads();
   }
 }
@@ -422,20 +444,20 @@ int launch_interior_dma(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hi
   return HHG_OK;
 }
 
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB>
+template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
 int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
   const int wl = h->wl_max;
   const size_t lds = 6 * (size_t)wl * sizeof(Pair<T>);
   ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
   if (h->persist_blocks > 0) {
-    auto kern = k_interior_persist<T, METHOD, RESID, CORR, A0, NW, TPB>;
+    auto kern = k_interior_persist<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>;
     if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(std::min(h->persist_blocks, h->n_work)), dim3(TPB), lds, st,
                        h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_work, h->n_work, x, k, f, y,
                        h->n_nodes, wl);
   } else {
-    auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB>;
+    auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>;
     if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
@@ -457,10 +479,12 @@ int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStr
     if (rounds <= 4) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 4>(h, x, k, f, y, st);
     if (rounds <= 5) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 5>(h, x, k, f, y, st);
   }
-  const int nw = (h->wl_max + h->chunk - 1) / h->chunk;
+  const int nw = (h->wl_max + 255) / 256;
   if (h->chunk == 256) {
-    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256>(h, x, k, f, y, st);
-    if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256>(h, x, k, f, y, st);
+    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256, 1>(h, x, k, f, y, st);
+    if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256, 1>(h, x, k, f, y, st);
+  } else if (h->chunk == 512) {
+    if (nw <= 4) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 4, 256, 2>(h, x, k, f, y, st);
   }
   return fail(HHG_EINVAL, "interior window larger than supported");
 }

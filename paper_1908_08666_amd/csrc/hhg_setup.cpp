@@ -632,7 +632,10 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   h->serial_apply = envs && std::atoi(envs) == 1;
   const char *envd = std::getenv("HHG_STAGE_DMA");
   h->stage_dma = envd && std::atoi(envd) == 1;
-  h->chunk = 256;
+  // positions per interior work item: 256 (one per thread) or 512 (two per
+  // thread: a smaller halo per position and more rows per barrier)
+  const char *envc = std::getenv("HHG_CHUNK");
+  h->chunk = (envc && std::atoi(envc) == 512) ? 512 : 256;
   {
     std::vector<int> all(M);
     for (int m = 0; m < M; ++m) all[m] = m;
