@@ -398,7 +398,8 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  * the launch stream.  hhg_profile_read synchronizes those events and returns,
  * per kernel id, the number of launches and the summed duration in ms since
  * enabling; ids: 0 interior scaled apply, 1 interior on-the-fly apply,
- * 2 macro-boundary rows, 3 copy-group sum, 4 solver vector kernels.
+ * 2 macro-boundary rows, 3 copy-group sum, 4 solver vector kernels,
+ * 5 learned smoother.
  * Enabling resets the counters.                                             */
 enum hhg_kernel_id {
   HHG_K_INTERIOR_SCALED = 0,

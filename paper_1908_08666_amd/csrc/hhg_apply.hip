@@ -7,57 +7,70 @@
 
 namespace hhg {
 
-// Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
-// computes the partial row of its macro; copies are summed afterwards.
-// ROWWISE: nodal integration for the whole row (also the on-the-fly method);
-// otherwise scaled entries towards macro-interior neighbours and nodal
-// entries towards macro-boundary neighbours and on the diagonal.  Every block
-// holds nodes of one macro, so the macro's constants are uniform loads.
+// Offset of plane k in a macro with n + 1 nodes per edge.
 __device__ __forceinline__ int plane_base32(int n, int k) {
   const int a = n + 1, b = n + 1 - k;
   return a * (a + 1) * (a + 2) / 6 - b * (b + 1) * (b + 2) / 6;
 }
 
-// One macro-boundary row of macro m at (i, j, k): the neighbours' positions
-// are classified at run time (inside the macro, on its boundary) and
-// Dirichlet values of x are masked.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
-__device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilConst<T> &sc,
-                                             const ElemConst<T> &ec, int i, int j, int k,
-                                             const uint8_t *__restrict__ flags,
-                                             const T *__restrict__ x, const T *__restrict__ kc,
-                                             const T *__restrict__ f, T *__restrict__ y,
-                                             int64_t nn) {
+// Neighbour data of one macro-boundary row at (i, j, k): which neighbours
+// lie inside the macro and which on its boundary, their coefficients and
+// their values of x (Dirichlet values masked), and the row's own values.
+template <typename T>
+struct BoundaryNbr {
+  bool in[NDIR], onb[NDIR];
+  T nx0[NDIR], nx1[NDIR], nx2[NDIR], nk[NDIR];
+  T ci0, ci1, ci2, ck;
+};
+
+template <typename T>
+__device__ __forceinline__ void boundary_gather(const MacroInfo &mi, int i, int j, int k,
+                                                const T *__restrict__ x, const T *__restrict__ kc,
+                                                int64_t nn, BoundaryNbr<T> &b) {
   const int n = mi.n;
   const T *X0 = x + mi.off;
   const T *X1 = X0 + nn;
   const T *X2 = X1 + nn;
   const T *KC = kc + mi.off;
-  const int lslot = plane_base32(n, k) + (i + j) * (i + j + 1) / 2 + i;
-  const int64_t slot = mi.off + lslot;
-  // neighbour data (inside the macro, on its boundary, Dirichlet-masked x)
-  bool in[NDIR], onb[NDIR];
-  T nx0[NDIR], nx1[NDIR], nx2[NDIR], nk[NDIR];
 #pragma unroll
   for (int d = 0; d < NDIR; ++d) {
     const int a = i + DIR_I[d], bb = j + DIR_J[d], cc = k + DIR_K[d];
-    in[d] = a >= 0 && bb >= 0 && cc >= 0 && a + bb + cc <= n;
-    onb[d] = false;
-    nx0[d] = nx1[d] = nx2[d] = nk[d] = T(0);
-    if (in[d]) {
+    b.in[d] = a >= 0 && bb >= 0 && cc >= 0 && a + bb + cc <= n;
+    b.onb[d] = false;
+    b.nx0[d] = b.nx1[d] = b.nx2[d] = b.nk[d] = T(0);
+    if (b.in[d]) {
       const int zz = zero_set(a, bb, cc, n);
-      onb[d] = zz != 0;
+      b.onb[d] = zz != 0;
       const int ls = plane_base32(n, cc) + (a + bb) * (a + bb + 1) / 2 + a;
-      nk[d] = KC[ls];
+      b.nk[d] = KC[ls];
       if (!((mi.dmask >> zz) & 1u)) {
-        nx0[d] = X0[ls];
-        nx1[d] = X1[ls];
-        nx2[d] = X2[ls];
+        b.nx0[d] = X0[ls];
+        b.nx1[d] = X1[ls];
+        b.nx2[d] = X2[ls];
       }
     }
   }
-  const T ci0 = X0[lslot], ci1 = X1[lslot], ci2 = X2[lslot];
-  const T ck = KC[lslot];
+  const int lslot = plane_base32(n, k) + (i + j) * (i + j + 1) / 2 + i;
+  b.ci0 = X0[lslot];
+  b.ci1 = X1[lslot];
+  b.ci2 = X2[lslot];
+  b.ck = KC[lslot];
+}
+
+// One macro-boundary row of macro m at (i, j, k) from its gathered
+// neighbour data: the macro's partial row (or, for a node without copies in
+// other macros and RESID, f minus the row) is written to the node's slot.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+__device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilConst<T> &sc,
+                                             const ElemConst<T> &ec, int i, int j, int k,
+                                             const BoundaryNbr<T> &b,
+                                             const uint8_t *__restrict__ flags,
+                                             const T *__restrict__ f, T *__restrict__ y,
+                                             int64_t nn) {
+  const int64_t slot = mi.off + plane_base32(mi.n, k) + (i + j) * (i + j + 1) / 2 + i;
+  const bool *in = b.in, *onb = b.onb;
+  const T *nx0 = b.nx0, *nx1 = b.nx1, *nx2 = b.nx2, *nk = b.nk;
+  const T ci0 = b.ci0, ci1 = b.ci1, ci2 = b.ci2, ck = b.ck;
   T y0 = T(0), y1 = T(0), y2 = T(0);
 #pragma unroll
   for (int t = 0; t < NTET; ++t) {
@@ -129,42 +142,82 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
   y[slot + 2 * nn] = y2;
 }
 
-// Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
-// computes the partial row of its macro; copies are summed afterwards.
-// ROWWISE: nodal integration for the whole row (also the on-the-fly method);
-// otherwise scaled entries towards macro-interior neighbours and nodal
-// entries towards macro-boundary neighbours and on the diagonal.  Every block
-// holds nodes of one macro (bblk), ordered by the boundary primitive they lie
-// on, so that a wave rarely diverges; Dirichlet slots of the macro's boundary
-// (flag bit 30 in bijk) get their zero rows here as well.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
-__global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
-    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
-    const ElemConst<T> *__restrict__ ecs, const int32_t *__restrict__ bijk,
-    const int32_t *__restrict__ bblk, const uint8_t *__restrict__ flags,
-    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn) {
-  // the macro's constants are staged in LDS and read from there by every
-  // row (scalar loads of 15 KB of constants would not fit the scalar
-  // registers); all lanes read the same address, so the reads broadcast
-  __shared__ __align__(16) unsigned char cbuf[sizeof(ElemConst<T>) + sizeof(StencilConst<T>)];
-  const int m = bblk[blockIdx.x];
-  {
-    static_assert(sizeof(ElemConst<T>) % 16 == 0 && sizeof(StencilConst<T>) % 4 == 0, "table sizes");
-    const uint4 *ge = reinterpret_cast<const uint4 *>(ecs + m);
-    const uint32_t *gs = reinterpret_cast<const uint32_t *>(scs + m);
-    uint4 *le = reinterpret_cast<uint4 *>(cbuf);
-    uint32_t *ls = reinterpret_cast<uint32_t *>(cbuf + sizeof(ElemConst<T>));
-    for (int q = threadIdx.x; q < (int)(sizeof(ElemConst<T>) / 16); q += BOUNDARY_BLOCK) le[q] = ge[q];
-    for (int q = threadIdx.x; q < (int)(sizeof(StencilConst<T>) / 4); q += BOUNDARY_BLOCK) ls[q] = gs[q];
+// Face coordinates: node (a, b) of layer l behind face f, and back.
+__device__ __forceinline__ void face_to_ijk(int f, int n, int a, int b, int l, int &i, int &j,
+                                            int &k) {
+  switch (f) {
+    case 0: i = a; j = b; k = n - a - b - l; break;
+    case 1: i = l; j = a; k = b; break;
+    case 2: i = a; j = l; k = b; break;
+    default: i = a; j = b; k = l;
   }
-  __syncthreads();
-  const int packed = bijk[(int64_t)blockIdx.x * BOUNDARY_BLOCK + threadIdx.x];
-  if (packed < 0) return;
+}
+__device__ __forceinline__ void ijk_to_face(int f, int n, int i, int j, int k, int &a, int &b,
+                                            int &l) {
+  switch (f) {
+    case 0: a = i; b = j; l = n - i - j - k; break;
+    case 1: a = j; b = k; l = i; break;
+    case 2: a = i; b = k; l = j; break;
+    default: a = i; b = j; l = k;
+  }
+}
+
+// The macro's constants (element blocks and stencil table) copied straight
+// into LDS by the loader, so staging costs no registers; all lanes later read
+// the same addresses, so the reads broadcast.  The caller waits for vmcnt(0)
+// and synchronizes before reading them.
+template <typename T>
+__device__ __forceinline__ void stage_constants(const StencilConst<T> *__restrict__ scs,
+                                                const ElemConst<T> *__restrict__ ecs, int m,
+                                                unsigned char *cbuf) {
+  static_assert(sizeof(ElemConst<T>) % 16 == 0 && sizeof(StencilConst<T>) % 4 == 0, "table sizes");
+  constexpr int EB = (int)sizeof(ElemConst<T>), SB = (int)sizeof(StencilConst<T>);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const char *ge = reinterpret_cast<const char *>(ecs + m);
+  const char *gs = reinterpret_cast<const char *>(scs + m);
+  for (int c = wave * 1024; c < EB; c += BOUNDARY_BLOCK * 16)      // wave-uniform
+    if (c + lane * 16 < EB)
+      __builtin_amdgcn_global_load_lds(ge + c + lane * 16,
+                                       (__attribute__((address_space(3))) void *)(cbuf + c), 16, 0, 0);
+  for (int c = wave * 256; c < SB; c += BOUNDARY_BLOCK * 4)
+    if (c + lane * 4 < SB)
+      __builtin_amdgcn_global_load_lds(gs + c + lane * 4,
+                                       (__attribute__((address_space(3))) void *)(cbuf + EB + c), 4, 0, 0);
+}
+
+template <typename T>
+constexpr int CONST_BYTES = (int)(sizeof(ElemConst<T>) + sizeof(StencilConst<T>));
+template <typename T>
+constexpr int TILE_BYTES = (int)(2 * 4 * FT_P * sizeof(T));
+
+// Block of BOUNDARY_BLOCK listed macro-boundary rows (edges, vertices, faces
+// without tiles, Dirichlet slots): every row gathers its neighbours from
+// HBM.  The rows of a block belong to one macro (bblk) and are ordered by the
+// boundary primitive they lie on, so that a wave rarely diverges; Dirichlet
+// slots (bit 30 in bijk) get their zero rows.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+__device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
+                                            const MacroInfo *__restrict__ minfo,
+                                            const StencilConst<T> *__restrict__ scs,
+                                            const ElemConst<T> *__restrict__ ecs,
+                                            const int32_t *__restrict__ bijk,
+                                            const int32_t *__restrict__ bblk,
+                                            const uint8_t *__restrict__ flags,
+                                            const T *__restrict__ x, const T *__restrict__ kc,
+                                            const T *__restrict__ f, T *__restrict__ y,
+                                            int64_t nn) {
+  const int m = bblk[blk];
+  const int packed = bijk[(int64_t)blk * BOUNDARY_BLOCK + threadIdx.x];
   const MacroInfo mi = minfo[m];
   const int i = packed & 1023, j = (packed >> 10) & 1023, k = (packed >> 20) & 1023;
-  const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(cbuf);
-  const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(cbuf + sizeof(ElemConst<T>));
+  // the row's neighbour loads go out first, the constants' copies behind
+  // them, so both are in flight together and one wait covers them
+  BoundaryNbr<T> nb;
+  if (packed >= 0 && !(packed & (1 << 30))) boundary_gather(mi, i, j, k, x, kc, nn, nb);
+  stage_constants(scs, ecs, m, smem);
+  __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
+  __syncthreads();
+  if (packed < 0) return;
   if (packed & (1 << 30)) {                // Dirichlet slot: its row is zero
     const int64_t slot = mi.off + plane_base32(mi.n, k) + (i + j) * (i + j + 1) / 2 + i;
     y[slot] = T(0);
@@ -172,7 +225,119 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
     y[slot + 2 * nn] = T(0);
     return;
   }
-  boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, flags, x, kc, f, y, nn);
+  const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(smem);
+  const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(smem + sizeof(ElemConst<T>));
+  boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+}
+
+// One FaceTile of rows inside a macro face: the tile's nodes and a halo of
+// one, in the face layer and in the first layer behind it, are staged in LDS
+// (each value is loaded once per tile instead of once per neighbouring row),
+// then every thread computes one row from there.  Dirichlet values of x are
+// masked when staged.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+__device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *smem,
+                                          const MacroInfo *__restrict__ minfo,
+                                          const StencilConst<T> *__restrict__ scs,
+                                          const ElemConst<T> *__restrict__ ecs,
+                                          const uint8_t *__restrict__ flags,
+                                          const T *__restrict__ x, const T *__restrict__ kc,
+                                          const T *__restrict__ f, T *__restrict__ y,
+                                          int64_t nn) {
+  static_assert(FT_W * FT_H == BOUNDARY_BLOCK, "one row per thread");
+  T(*tile)[4][FT_P] = reinterpret_cast<T(*)[4][FT_P]>(smem + CONST_BYTES<T>);  // [layer][x0 x1 x2 k]
+  const int m = ft.macro;
+  const MacroInfo mi = minfo[m];
+  const int n = mi.n;
+  const int fc = __builtin_amdgcn_readfirstlane(ft.face);
+  const int a0 = ft.a0, b0 = ft.b0;
+  const int tid = threadIdx.x;
+  // staging loads: entry q of 2 * FT_P is (layer, halo row, halo column)
+  constexpr int NR = (2 * FT_P + BOUNDARY_BLOCK - 1) / BOUNDARY_BLOCK;
+  T v[NR][4];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int q = r * BOUNDARY_BLOCK + tid;
+    const int l = q / FT_P, p = q - l * FT_P;
+    const int a = a0 - 1 + p % (FT_W + 2), b = b0 - 1 + p / (FT_W + 2);
+    v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
+    if (q < 2 * FT_P && a >= 0 && b >= 0 && a + b + l <= n) {
+      int i, j, k;
+      face_to_ijk(fc, n, a, b, l, i, j, k);
+      const int64_t ls = mi.off + plane_base32(n, k) + (i + j) * (i + j + 1) / 2 + i;
+      v[r][3] = kc[ls];
+      if (!((mi.dmask >> zero_set(i, j, k, n)) & 1u)) {
+        v[r][0] = x[ls];
+        v[r][1] = x[nn + ls];
+        v[r][2] = x[2 * nn + ls];
+      }
+    }
+  }
+  stage_constants(scs, ecs, m, smem);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int q = r * BOUNDARY_BLOCK + tid;
+    if (q < 2 * FT_P) {
+      const int l = q / FT_P, p = q - l * FT_P;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) tile[l][c][p] = v[r][c];
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
+  __syncthreads();
+  const int a = a0 + tid % FT_W, b = b0 + tid / FT_W;
+  if (a + b > n - 1) return;               // a, b >= 1 by construction
+  int i, j, k;
+  face_to_ijk(fc, n, a, b, 0, i, j, k);
+  BoundaryNbr<T> nb;
+#pragma unroll
+  for (int d = 0; d < NDIR; ++d) {
+    const int ii = i + DIR_I[d], jj = j + DIR_J[d], kk = k + DIR_K[d];
+    nb.in[d] = ii >= 0 && jj >= 0 && kk >= 0 && ii + jj + kk <= n;
+    nb.onb[d] = false;
+    nb.nx0[d] = nb.nx1[d] = nb.nx2[d] = nb.nk[d] = T(0);
+    if (nb.in[d]) {
+      int ap, bp, lp;
+      ijk_to_face(fc, n, ii, jj, kk, ap, bp, lp);
+      const int p = (ap - a0 + 1) + (bp - b0 + 1) * (FT_W + 2);
+      nb.onb[d] = zero_set(ii, jj, kk, n) != 0;
+      nb.nx0[d] = tile[lp][0][p];
+      nb.nx1[d] = tile[lp][1][p];
+      nb.nx2[d] = tile[lp][2][p];
+      nb.nk[d] = tile[lp][3][p];
+    }
+  }
+  const int pc = (a - a0 + 1) + (b - b0 + 1) * (FT_W + 2);
+  nb.ci0 = tile[0][0][pc];
+  nb.ci1 = tile[0][1][pc];
+  nb.ci2 = tile[0][2][pc];
+  nb.ck = tile[0][3][pc];
+  const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(smem);
+  const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(smem + sizeof(ElemConst<T>));
+  boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+}
+
+// Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
+// computes the partial row of its macro; copies are summed afterwards.
+// ROWWISE: nodal integration for the whole row (also the on-the-fly method);
+// otherwise scaled entries towards macro-interior neighbours and nodal
+// entries towards macro-boundary neighbours and on the diagonal.  One launch
+// covers all of them: the first nft blocks are face tiles, the rest blocks
+// of listed rows, so that the whole boundary is queued at once.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+__global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
+    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
+    const ElemConst<T> *__restrict__ ecs, const FaceTile *__restrict__ tiles, int nft,
+    const int32_t *__restrict__ bijk, const int32_t *__restrict__ bblk,
+    const uint8_t *__restrict__ flags, const T *__restrict__ x, const T *__restrict__ kc,
+    const T *__restrict__ f, T *__restrict__ y, int64_t nn) {
+  __shared__ __align__(16) unsigned char smem[CONST_BYTES<T> + TILE_BYTES<T>];
+  if ((int)blockIdx.x < nft)
+    face_rows<T, RESID, ROWWISE, CORR, A0>(tiles[blockIdx.x], smem, minfo, scs, ecs, flags, x, kc,
+                                           f, y, nn);
+  else
+    listed_rows<T, RESID, ROWWISE, CORR, A0>((int)blockIdx.x - nft, smem, minfo, scs, ecs, bijk,
+                                             bblk, flags, x, kc, f, y, nn);
 }
 
 // Sum of the partial rows of all copies of an interface node; the total (or
@@ -215,12 +380,14 @@ int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, 
                     hipStream_t st) {
   const bool rowwise = method == METHOD_ONTHEFLY || h->op.iface == HHG_IFACE_ROWWISE;
   const bool corr = h->op.corr == HHG_CORR_PHYSICAL;
-  if (!h->bblk.empty()) {
-    const dim3 grid((unsigned)h->bblk.size());
+  const int nft = (int)h->ftile.size();
+  const int nblk = nft + (int)h->bblk.size();
+  if (nblk > 0) {
+    const dim3 grid((unsigned)nblk);
 #define HHG_LB(RW, CR, A0)                                                                       \
   hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR, A0>), grid, dim3(BOUNDARY_BLOCK), 0, st, \
-                     h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_bijk, h->d_bblk, h->d_flags, x, \
-                     k, f, y, h->n_nodes)
+                     h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_ftile, nft, h->d_bijk,          \
+                     h->d_bblk, h->d_flags, x, k, f, y, h->n_nodes)
     ProfScope prof(h, HHG_K_BOUNDARY_ROWS, st);
     const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
     if (rowwise) {

@@ -25,6 +25,7 @@ struct hhg_ctx {
   std::vector<hhg::WorkItem> work;
   std::vector<int32_t> bijk;                 // non-Dirichlet boundary slots, packed (i,j,k)
   std::vector<int32_t> bblk;                 // macro of each boundary-row block
+  std::vector<hhg::FaceTile> ftile;          // tiles of face-interior rows (non-Dirichlet faces)
   std::vector<int64_t> dslot;                // Dirichlet slots (rows written as zero)
   std::vector<int64_t> grp_ptr, grp_slot;    // non-Dirichlet copy groups
   std::vector<int64_t> agrp_ptr, agrp_slot;  // all copy groups
@@ -48,6 +49,7 @@ struct hhg_ctx {
   int n_work = 0;
   int32_t *d_bijk = nullptr;
   int32_t *d_bblk = nullptr;
+  hhg::FaceTile *d_ftile = nullptr;
   int64_t *d_dslot = nullptr;
   int64_t *d_grp_ptr = nullptr;              // interface copy groups (>= 2 copies)
   int64_t *d_grp_slot = nullptr;

@@ -111,6 +111,17 @@ struct WorkItem {
 };
 
 constexpr int BOUNDARY_BLOCK = 256;  // threads per block of the boundary-row kernel
+
+// A tile of rows inside one face of a macro, in the face's own coordinates
+// (a, b) with the face layer l = 0 and the macro's layers l = 1, 2, ... behind
+// it; face f is the one whose nodes have barycentric coordinate f equal to
+// zero (0: i + j + k = n, 1: i = 0, 2: j = 0, 3: k = 0).  Rows a0 <= a <
+// a0 + FT_W, b0 <= b < b0 + FT_H with a, b >= 1 and a + b <= n - 1.
+struct FaceTile {
+  int32_t macro, face, a0, b0;
+};
+constexpr int FT_W = 32, FT_H = 8;             // rows per tile: FT_W * FT_H = BOUNDARY_BLOCK
+constexpr int FT_P = (FT_W + 2) * (FT_H + 2);  // tile positions with their halo, per layer
 constexpr int NXCD = 8;              // accelerator complex dies of an MI355X
 
 }  // namespace hhg

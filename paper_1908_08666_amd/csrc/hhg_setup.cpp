@@ -372,6 +372,7 @@ void free_ctx(hhg_ctx *h) {
   dfree(h->d_work);
   dfree(h->d_bijk);
   dfree(h->d_bblk);
+  dfree(h->d_ftile);
   dfree(h->d_dslot);
   dfree(h->d_grp_ptr);
   dfree(h->d_grp_slot);
@@ -588,9 +589,20 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   // each macro padded to whole blocks so that a block sees a single macro
   std::vector<int32_t> bijk, bblk;
   std::vector<int64_t> dslot;
+  std::vector<FaceTile> ftile;
   {
     size_t q = 0;
     for (int m = 0; m < M; ++m) {
+      // rows inside a non-Dirichlet face are computed in face tiles, whose
+      // two layers are staged in LDS once for all rows of the tile
+      bool tiled[4];
+      const int nm = h->minfo[m].n;
+      for (int f = 0; f < 4; ++f) {
+        tiled[f] = nm >= 3 && !((h->minfo[m].dmask >> (1u << f)) & 1u);
+        if (!tiled[f]) continue;
+        for (int b0 = 1; b0 <= nm - 2; b0 += FT_H)
+          for (int a0 = 1; a0 + b0 <= nm - 1; a0 += FT_W) ftile.push_back({m, f, a0, b0});
+      }
       size_t cnt = 0;
       // rows of one boundary primitive (face, edge, vertex) together, so that
       // the waves of the boundary-row kernel rarely diverge; then the
@@ -607,6 +619,7 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
           continue;
         }
         const int z = ((n - i - j - k) == 0) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3);
+        if ((z & (z - 1)) == 0 && tiled[__builtin_ctz(z)]) continue;   // in a face tile
         rows.push_back({z, bslot[q].y});
       }
       std::stable_sort(rows.begin(), rows.end(),
@@ -645,6 +658,7 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
 
   h->bijk = std::move(bijk);
   h->bblk = std::move(bblk);
+  h->ftile = std::move(ftile);
   h->dslot = std::move(dslot);
   h->grp_ptr = std::move(gptr);
   h->grp_slot = std::move(gslot);
@@ -714,6 +728,7 @@ int ensure_device(hhg_ctx *h) {
   if ((rc = upload(&h->d_work, h->work.data(), h->work.size()))) return rc;
   if ((rc = upload(&h->d_bijk, h->bijk.data(), h->bijk.size()))) return rc;
   if ((rc = upload(&h->d_bblk, h->bblk.data(), h->bblk.size()))) return rc;
+  if ((rc = upload(&h->d_ftile, h->ftile.data(), h->ftile.size()))) return rc;
   if ((rc = upload(&h->d_dslot, h->dslot.data(), h->dslot.size()))) return rc;
   if ((rc = upload(&h->d_grp_ptr, h->grp_ptr.data(), h->grp_ptr.size()))) return rc;
   if ((rc = upload(&h->d_grp_slot, h->grp_slot.data(), h->grp_slot.size()))) return rc;
