@@ -230,12 +230,32 @@ __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
   boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
 }
 
-// One FaceTile of rows inside a macro face: the tile's nodes and a halo of
-// one, in the face layer and in the first layer behind it, are staged in LDS
-// (each value is loaded once per tile instead of once per neighbouring row),
-// then every thread computes one row from there.  Dirichlet values of x are
-// masked when staged.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+// Displacement (da, db, dl) in face coordinates of lattice direction d for
+// face FACE (see face_to_ijk).
+template <int FACE>
+__host__ __device__ constexpr int face_da(int d) {
+  return FACE == 1 ? DIR_J[d] : DIR_I[d];
+}
+template <int FACE>
+__host__ __device__ constexpr int face_db(int d) {
+  return FACE == 0 || FACE == 3 ? DIR_J[d] : DIR_K[d];
+}
+template <int FACE>
+__host__ __device__ constexpr int face_dl(int d) {
+  return FACE == 0 ? -(DIR_I[d] + DIR_J[d] + DIR_K[d])
+                   : (FACE == 1 ? DIR_I[d] : (FACE == 2 ? DIR_J[d] : DIR_K[d]));
+}
+
+// One FaceTile of deep rows of a macro face (face coordinates a, b >= 2 and
+// n - a - b >= 2): the tile's nodes and a halo of one, in the face layer and
+// in the first layer behind it, are staged in LDS (each value is loaded once
+// per tile instead of once per neighbouring row; Dirichlet values of x are
+// masked), then every thread computes one row from there.  For a deep row
+// the neighbours in the face layer lie on the face, those in the first
+// layer inside the macro and those in front of the face outside it, so with
+// the face fixed at compile time every neighbour's role and LDS offset is a
+// constant and the row needs no branches.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, int FACE>
 __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *smem,
                                           const MacroInfo *__restrict__ minfo,
                                           const StencilConst<T> *__restrict__ scs,
@@ -249,7 +269,6 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
   const int m = ft.macro;
   const MacroInfo mi = minfo[m];
   const int n = mi.n;
-  const int fc = __builtin_amdgcn_readfirstlane(ft.face);
   const int a0 = ft.a0, b0 = ft.b0;
   const int tid = threadIdx.x;
   // staging loads: entry q of 2 * FT_P is (layer, halo row, halo column)
@@ -263,7 +282,7 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
     v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
     if (q < 2 * FT_P && a >= 0 && b >= 0 && a + b + l <= n) {
       int i, j, k;
-      face_to_ijk(fc, n, a, b, l, i, j, k);
+      face_to_ijk(FACE, n, a, b, l, i, j, k);
       const int64_t ls = mi.off + plane_base32(n, k) + (i + j) * (i + j + 1) / 2 + i;
       v[r][3] = kc[ls];
       if (!((mi.dmask >> zero_set(i, j, k, n)) & 1u)) {
@@ -286,28 +305,25 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
   __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
   __syncthreads();
   const int a = a0 + tid % FT_W, b = b0 + tid / FT_W;
-  if (a + b > n - 1) return;               // a, b >= 1 by construction
+  if (a + b > n - 2) return;               // a, b >= 2 by construction
   int i, j, k;
-  face_to_ijk(fc, n, a, b, 0, i, j, k);
+  face_to_ijk(FACE, n, a, b, 0, i, j, k);
+  const int pc = (a - a0 + 1) + (b - b0 + 1) * (FT_W + 2);
   BoundaryNbr<T> nb;
 #pragma unroll
   for (int d = 0; d < NDIR; ++d) {
-    const int ii = i + DIR_I[d], jj = j + DIR_J[d], kk = k + DIR_K[d];
-    nb.in[d] = ii >= 0 && jj >= 0 && kk >= 0 && ii + jj + kk <= n;
-    nb.onb[d] = false;
+    const int dl = face_dl<FACE>(d);
+    nb.in[d] = dl >= 0;
+    nb.onb[d] = dl == 0;
     nb.nx0[d] = nb.nx1[d] = nb.nx2[d] = nb.nk[d] = T(0);
-    if (nb.in[d]) {
-      int ap, bp, lp;
-      ijk_to_face(fc, n, ii, jj, kk, ap, bp, lp);
-      const int p = (ap - a0 + 1) + (bp - b0 + 1) * (FT_W + 2);
-      nb.onb[d] = zero_set(ii, jj, kk, n) != 0;
-      nb.nx0[d] = tile[lp][0][p];
-      nb.nx1[d] = tile[lp][1][p];
-      nb.nx2[d] = tile[lp][2][p];
-      nb.nk[d] = tile[lp][3][p];
+    if (dl >= 0) {
+      const int p = pc + face_da<FACE>(d) + face_db<FACE>(d) * (FT_W + 2);
+      nb.nx0[d] = tile[dl][0][p];
+      nb.nx1[d] = tile[dl][1][p];
+      nb.nx2[d] = tile[dl][2][p];
+      nb.nk[d] = tile[dl][3][p];
     }
   }
-  const int pc = (a - a0 + 1) + (b - b0 + 1) * (FT_W + 2);
   nb.ci0 = tile[0][0][pc];
   nb.ci1 = tile[0][1][pc];
   nb.ci2 = tile[0][2][pc];
@@ -332,10 +348,19 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
     const uint8_t *__restrict__ flags, const T *__restrict__ x, const T *__restrict__ kc,
     const T *__restrict__ f, T *__restrict__ y, int64_t nn) {
   __shared__ __align__(16) unsigned char smem[CONST_BYTES<T> + TILE_BYTES<T>];
-  if ((int)blockIdx.x < nft)
-    face_rows<T, RESID, ROWWISE, CORR, A0>(tiles[blockIdx.x], smem, minfo, scs, ecs, flags, x, kc,
-                                           f, y, nn);
-  else
+  if ((int)blockIdx.x < nft) {
+    const FaceTile ft = tiles[blockIdx.x];
+    switch (__builtin_amdgcn_readfirstlane(ft.face)) {
+#define HHG_FR(F)                                                                                 \
+  face_rows<T, RESID, ROWWISE, CORR, A0, F>(ft, smem, minfo, scs, ecs, flags, x, kc, f, y, nn); \
+  break
+      case 0: HHG_FR(0);
+      case 1: HHG_FR(1);
+      case 2: HHG_FR(2);
+      default: HHG_FR(3);
+#undef HHG_FR
+    }
+  } else
     listed_rows<T, RESID, ROWWISE, CORR, A0>((int)blockIdx.x - nft, smem, minfo, scs, ecs, bijk,
                                              bblk, flags, x, kc, f, y, nn);
 }

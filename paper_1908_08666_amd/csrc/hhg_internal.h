@@ -116,7 +116,8 @@ constexpr int BOUNDARY_BLOCK = 256;  // threads per block of the boundary-row ke
 // (a, b) with the face layer l = 0 and the macro's layers l = 1, 2, ... behind
 // it; face f is the one whose nodes have barycentric coordinate f equal to
 // zero (0: i + j + k = n, 1: i = 0, 2: j = 0, 3: k = 0).  Rows a0 <= a <
-// a0 + FT_W, b0 <= b < b0 + FT_H with a, b >= 1 and a + b <= n - 1.
+// a0 + FT_W, b0 <= b < b0 + FT_H with a, b >= 2 and a + b <= n - 2 (the
+// face's deep rows, two or more nodes away from its edges).
 struct FaceTile {
   int32_t macro, face, a0, b0;
 };

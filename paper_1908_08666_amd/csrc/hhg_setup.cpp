@@ -598,10 +598,10 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
       bool tiled[4];
       const int nm = h->minfo[m].n;
       for (int f = 0; f < 4; ++f) {
-        tiled[f] = nm >= 3 && !((h->minfo[m].dmask >> (1u << f)) & 1u);
+        tiled[f] = nm >= 6 && !((h->minfo[m].dmask >> (1u << f)) & 1u);
         if (!tiled[f]) continue;
-        for (int b0 = 1; b0 <= nm - 2; b0 += FT_H)
-          for (int a0 = 1; a0 + b0 <= nm - 1; a0 += FT_W) ftile.push_back({m, f, a0, b0});
+        for (int b0 = 2; b0 <= nm - 4; b0 += FT_H)
+          for (int a0 = 2; a0 + b0 <= nm - 2; a0 += FT_W) ftile.push_back({m, f, a0, b0});
       }
       size_t cnt = 0;
       // rows of one boundary primitive (face, edge, vertex) together, so that
@@ -619,7 +619,12 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
           continue;
         }
         const int z = ((n - i - j - k) == 0) | ((i == 0) << 1) | ((j == 0) << 2) | ((k == 0) << 3);
-        if ((z & (z - 1)) == 0 && tiled[__builtin_ctz(z)]) continue;   // in a face tile
+        if ((z & (z - 1)) == 0 && tiled[__builtin_ctz(z)]) {
+          // deep rows of a tiled face (face coordinates a, b, n - a - b >= 2)
+          const int f = __builtin_ctz(z);
+          const int fa = f == 1 ? j : i, fb = (f == 0 || f == 3) ? j : k;
+          if (fa >= 2 && fb >= 2 && n - fa - fb >= 2) continue;   // in a face tile
+        }
         rows.push_back({z, bslot[q].y});
       }
       std::stable_sort(rows.begin(), rows.end(),
