@@ -103,6 +103,23 @@ def test_cube24_eps_operator(dtype):
     check(lib, orc, s2n, k, EPS, x, dtype, "onthefly")
 
 
+@pytest.mark.parametrize("op,dtype", [("lame1", torch.float64), ("lame1", torch.float32),
+                                      ("eform", torch.float64)])
+def test_unit_tet_level6_all_faces_tiled(op, dtype):
+    """One macro at level 6 (47,905 nodes) without Dirichlet nodes: all four
+    faces are macro-boundary faces, each cut into several 32 x 8 tiles of
+    deep rows in both face directions, with the rim of each face, the edges
+    and the vertices on the listed-row path.  Full scaled and on-the-fly
+    applies against the oracle, with (mu = 1) and without (E-form) an
+    unscaled part of the form."""
+    opd = {"lame1": LAME1, "eform": EFORM}[op]
+    lib, orc, s2n = setup_case(W.unit_tet(), 6, opd, dirichlet="none")
+    k = W.sine_coefficient(orc.xyz) + 0.2
+    x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(1, 600)).reshape(-1, 3)
+    check(lib, orc, s2n, k, opd, x, dtype, "scaled")
+    check(lib, orc, s2n, k, opd, x, dtype, "onthefly")
+
+
 @pytest.mark.parametrize("variant", [dict(corr="none"), dict(khat="edge")])
 def test_variants(variant):
     lib, orc, s2n = setup_case(W.kuhn6(), 3, EFORM, **variant)
