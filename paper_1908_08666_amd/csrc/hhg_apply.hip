@@ -185,6 +185,8 @@ __device__ __forceinline__ void stage_constants(const StencilConst<T> *__restric
                                        (__attribute__((address_space(3))) void *)(cbuf + EB + c), 4, 0, 0);
 }
 
+constexpr int FT_RPT = FT_W * FT_H / BOUNDARY_BLOCK;   // face-tile rows per thread
+
 template <typename T>
 constexpr int CONST_BYTES = (int)(sizeof(ElemConst<T>) + sizeof(StencilConst<T>));
 template <typename T>
@@ -210,10 +212,20 @@ __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
   const int packed = bijk[(int64_t)blk * BOUNDARY_BLOCK + threadIdx.x];
   const MacroInfo mi = minfo[m];
   const int i = packed & 1023, j = (packed >> 10) & 1023, k = (packed >> 20) & 1023;
+  const bool live = packed >= 0 && !(packed & (1 << 30));
+  if (!__syncthreads_or(live)) {           // a block of Dirichlet slots only
+    if (packed >= 0) {
+      const int64_t slot = mi.off + plane_base32(mi.n, k) + (i + j) * (i + j + 1) / 2 + i;
+      y[slot] = T(0);
+      y[slot + nn] = T(0);
+      y[slot + 2 * nn] = T(0);
+    }
+    return;
+  }
   // the row's neighbour loads go out first, the constants' copies behind
   // them, so both are in flight together and one wait covers them
   BoundaryNbr<T> nb;
-  if (packed >= 0 && !(packed & (1 << 30))) boundary_gather(mi, i, j, k, x, kc, nn, nb);
+  if (live) boundary_gather(mi, i, j, k, x, kc, nn, nb);
   stage_constants(scs, ecs, m, smem);
   __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
   __syncthreads();
@@ -250,7 +262,7 @@ __host__ __device__ constexpr int face_dl(int d) {
 // n - a - b >= 2): the tile's nodes and a halo of one, in the face layer and
 // in the first layer behind it, are staged in LDS (each value is loaded once
 // per tile instead of once per neighbouring row; Dirichlet values of x are
-// masked), then every thread computes one row from there.  For a deep row
+// masked), then every thread computes FT_RPT rows from there.  For a deep row
 // the neighbours in the face layer lie on the face, those in the first
 // layer inside the macro and those in front of the face outside it, so with
 // the face fixed at compile time every neighbour's role and LDS offset is a
@@ -264,7 +276,7 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
                                           const T *__restrict__ x, const T *__restrict__ kc,
                                           const T *__restrict__ f, T *__restrict__ y,
                                           int64_t nn) {
-  static_assert(FT_W * FT_H == BOUNDARY_BLOCK, "one row per thread");
+  static_assert(FT_RPT * BOUNDARY_BLOCK == FT_W * FT_H && FT_H % FT_RPT == 0, "whole rows per thread");
   T(*tile)[4][FT_P] = reinterpret_cast<T(*)[4][FT_P]>(smem + CONST_BYTES<T>);  // [layer][x0 x1 x2 k]
   const int m = ft.macro;
   const MacroInfo mi = minfo[m];
@@ -304,33 +316,41 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
   __syncthreads();
-  const int a = a0 + tid % FT_W, b = b0 + tid / FT_W;
-  if (a + b > n - 2) return;               // a, b >= 2 by construction
-  int i, j, k;
-  face_to_ijk(FACE, n, a, b, 0, i, j, k);
-  const int pc = (a - a0 + 1) + (b - b0 + 1) * (FT_W + 2);
-  BoundaryNbr<T> nb;
+#pragma unroll 1
+  for (int r = 0; r < FT_RPT; ++r) {       // rows b0 + tid / FT_W + r * FT_H / FT_RPT
+    // the constants' LDS base is made opaque in every iteration, so that
+    // their reads are not hoisted out of the loop into registers
+    int coff = 0;
+    asm volatile("" : "+v"(coff));
+    const unsigned char *cb = smem + coff;
+    const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(cb);
+    const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(cb + sizeof(ElemConst<T>));
+    const int a = a0 + tid % FT_W, b = b0 + tid / FT_W + r * (FT_H / FT_RPT);
+    if (a + b > n - 2) continue;           // a, b >= 2 by construction
+    int i, j, k;
+    face_to_ijk(FACE, n, a, b, 0, i, j, k);
+    const int pc = (a - a0 + 1) + (b - b0 + 1) * (FT_W + 2);
+    BoundaryNbr<T> nb;
 #pragma unroll
-  for (int d = 0; d < NDIR; ++d) {
-    const int dl = face_dl<FACE>(d);
-    nb.in[d] = dl >= 0;
-    nb.onb[d] = dl == 0;
-    nb.nx0[d] = nb.nx1[d] = nb.nx2[d] = nb.nk[d] = T(0);
-    if (dl >= 0) {
-      const int p = pc + face_da<FACE>(d) + face_db<FACE>(d) * (FT_W + 2);
-      nb.nx0[d] = tile[dl][0][p];
-      nb.nx1[d] = tile[dl][1][p];
-      nb.nx2[d] = tile[dl][2][p];
-      nb.nk[d] = tile[dl][3][p];
+    for (int d = 0; d < NDIR; ++d) {
+      const int dl = face_dl<FACE>(d);
+      nb.in[d] = dl >= 0;
+      nb.onb[d] = dl == 0;
+      nb.nx0[d] = nb.nx1[d] = nb.nx2[d] = nb.nk[d] = T(0);
+      if (dl >= 0) {
+        const int p = pc + face_da<FACE>(d) + face_db<FACE>(d) * (FT_W + 2);
+        nb.nx0[d] = tile[dl][0][p];
+        nb.nx1[d] = tile[dl][1][p];
+        nb.nx2[d] = tile[dl][2][p];
+        nb.nk[d] = tile[dl][3][p];
+      }
     }
+    nb.ci0 = tile[0][0][pc];
+    nb.ci1 = tile[0][1][pc];
+    nb.ci2 = tile[0][2][pc];
+    nb.ck = tile[0][3][pc];
+    boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
   }
-  nb.ci0 = tile[0][0][pc];
-  nb.ci1 = tile[0][1][pc];
-  nb.ci2 = tile[0][2][pc];
-  nb.ck = tile[0][3][pc];
-  const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(smem);
-  const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(smem + sizeof(ElemConst<T>));
-  boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
 }
 
 // Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
@@ -455,17 +475,18 @@ int apply_t(hhg_ctx *h, int method, const T *f, const T *x, const T *k, T *y, hi
   // which fills every compute unit, it would only start as that one drains
   HHG_HIP(hipEventRecord(h->ev_fork, st));
   HHG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  hipStream_t sb = h->side, si = st;
   int rc;
   if (f) {
-    rc = launch_boundary<T, true>(h, method, x, k, f, y, h->side);
+    rc = launch_boundary<T, true>(h, method, x, k, f, y, sb);
     if (!rc)
-      rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, true>(h, x, k, f, y, st)
-                                   : launch_interior_v<T, METHOD_ONTHEFLY, true>(h, x, k, f, y, st);
+      rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, true>(h, x, k, f, y, si)
+                                   : launch_interior_v<T, METHOD_ONTHEFLY, true>(h, x, k, f, y, si);
   } else {
-    rc = launch_boundary<T, false>(h, method, x, k, f, y, h->side);
+    rc = launch_boundary<T, false>(h, method, x, k, f, y, sb);
     if (!rc)
-      rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, st)
-                                   : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, st);
+      rc = method == METHOD_SCALED ? launch_interior_v<T, METHOD_SCALED, false>(h, x, k, f, y, si)
+                                   : launch_interior_v<T, METHOD_ONTHEFLY, false>(h, x, k, f, y, si);
   }
   HHG_HIP(hipEventRecord(h->ev_join, h->side));
   HHG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));
