@@ -21,6 +21,10 @@ Newtonian fluids"):
 * ``strain``     nodal strain rate by local least squares (Sec. 3, eq.
                  minimization_problem) and the Carreau law (eq. carreau).
 * ``solvers``    reference solves (SciPy) used to judge the GPU solvers.
+* ``multigrid``  P1 prolongation between refinement levels, coefficient
+                 injection, rediscretised level operators, V(nu1, nu2) cycles
+                 with damped block-Jacobi smoothing and V-cycle-preconditioned
+                 CG (Sec. 5 and 6).
 
 Parity status of each function is stated in its docstring; functions whose
 results are pinned only against themselves say "parity unpinned".
