@@ -393,6 +393,63 @@ int hhg_mlp_train(hhg_mlp m, const void *samples, int64_t n, const hhg_train_opt
  * handle does not own it: keep it alive while solves use it.               */
 int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
 
+/* Geometric multigrid on the hierarchy of uniform refinements (the paper's
+ * solver, Sec. 5 and 6), for the scaled operator (interface rule of the
+ * op descriptor, FP64):
+ *   * one library handle per level coarse_level..L of the same conforming
+ *     macro mesh (L = mesh->level[0]);
+ *   * prolongation P: P1 interpolation from level l to l + 1 (a fine node
+ *     that is a coarse node copies it, every other fine node is the midpoint
+ *     of one coarse lattice edge and takes the mean of its end values);
+ *     restriction R = P^T;
+ *   * level operators rediscretised with the coefficient injected from the
+ *     finest level (coarse node value = value at the same fine node);
+ *   * smoother: damped block Jacobi x += omega D^-1 (b - A x), D the 3x3
+ *     diagonal blocks (the paper smooths with a hybrid Gauss-Seidel);
+ *   * coarsest level: exact solve with the inverse of the assembled operator
+ *     (at most 512 unknown nodes, e.g. level 2);
+ *   * hhg_mg_solve: CG preconditioned by one V(nu1, nu2) cycle per iteration.
+ * Vectors are slot vectors of the level's handle ([3][n_nodes], FP64,
+ * consistent, 16-byte aligned); Dirichlet entries are ignored on input and
+ * written 0.  The caller owns every vector and the workspace
+ * (hhg_mg_workspace_bytes, 256-byte aligned), which holds the per-level
+ * coefficients, inverse blocks, vectors and the coarse inverse between
+ * hhg_mg_setup_coefficient and the cycles that use them.  Calls are
+ * asynchronous on the stream except hhg_mg_create, hhg_mg_setup_coefficient
+ * (synchronizes) and hhg_mg_solve (synchronizes once per iteration to test
+ * convergence).  Errors: HHG_EINVAL (null or misaligned pointer, level out of
+ * range, non-conforming mesh, coarse level with more than 512 unknown nodes,
+ * nu1 + nu2 < 1, omega outside (0, 2)), HHG_EHIP, HHG_EBREAKDOWN (coarse
+ * operator not SPD, or CG breakdown), HHG_ENOCONV (maxit reached; x and info
+ * are written).                                                            */
+typedef struct hhg_mg_s *hhg_mg;
+typedef struct {
+  int32_t nu1, nu2;      /* pre- and post-smoothing steps (paper: 3, 3)      */
+  double omega;          /* block-Jacobi damping, e.g. 0.7                    */
+  double rtol;           /* hhg_mg_solve: ||b - A x|| <= rtol ||b||           */
+  int32_t maxit;         /* hhg_mg_solve: CG iterations allowed               */
+  int32_t pad;
+} hhg_mg_opts;
+int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coarse_level,
+                  hhg_mg *out);
+int hhg_mg_destroy(hhg_mg mg);
+/* handle of one level (owned by mg: do not destroy it) */
+int hhg_mg_level(hhg_mg mg, int32_t level, hhg_handle *out);
+int hhg_mg_workspace_bytes(hhg_mg mg, size_t *bytes);
+/* xf = P xc: xc on level fine_level - 1, xf on fine_level */
+int hhg_mg_prolong(hhg_mg mg, int32_t fine_level, const double *xc, double *xf, void *stream);
+/* rc = P^T rf (rc consistent over the copies; Dirichlet entries 0) */
+int hhg_mg_restrict(hhg_mg mg, int32_t fine_level, const double *rf, double *rc, void *stream);
+/* k: FP64 [n_nodes] coefficient of the finest level; injects it, builds the
+ * inverse blocks of every level and the coarse inverse in the workspace */
+int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *stream);
+/* z = V(r): one V(nu1, nu2) cycle on the finest level from z = 0 */
+int hhg_mg_vcycle(hhg_mg mg, const hhg_mg_opts *o, const double *r, double *z, void *workspace,
+                  void *stream);
+/* x: start vector on input, solution on output (finest level) */
+int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, void *workspace,
+                 hhg_solve_info *info, void *stream);
+
 /* Kernel timing (tracing aid, not needed for results).  While enabled,
  * every kernel the library launches is bracketed by a pair of HIP events on
  * the launch stream.  hhg_profile_read synchronizes those events and returns,

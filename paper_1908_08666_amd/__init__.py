@@ -5,6 +5,6 @@ The compute path is the HIP library ``libhhg.so`` (C ABI in include/hhg.h);
 this package only marshals arguments.  Importing it does not load the library;
 the first handle does, and fails loudly if it is missing.
 """
-from .hhg import Mesh  # noqa: F401
+from .hhg import Mesh, Multigrid  # noqa: F401
 
-__all__ = ["Mesh"]
+__all__ = ["Mesh", "Multigrid"]

@@ -54,6 +54,11 @@ HHG_MLP_NPARAM = 16 * 64 + 64 + 64 * 9 + 9
 HHG_SAMPLE_BYTES = 128
 
 
+class MgOpts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class TrainOpts(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
@@ -117,6 +122,17 @@ SIGNATURES = {
                       ctypes.c_int),
     "hhg_set_learned_model": ([_VP, _VP], ctypes.c_int),
     "hhg_preconditioner": ([_VP, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(OpDesc), _I32, ctypes.POINTER(_VP)],
+                      ctypes.c_int),
+    "hhg_mg_destroy": ([_VP], ctypes.c_int),
+    "hhg_mg_level": ([_VP, _I32, ctypes.POINTER(_VP)], ctypes.c_int),
+    "hhg_mg_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hhg_mg_prolong": ([_VP, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_restrict": ([_VP, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_setup_coefficient": ([_VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_vcycle": ([_VP, ctypes.POINTER(MgOpts), _VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_solve": ([_VP, ctypes.POINTER(MgOpts), _VP, _VP, _VP, ctypes.POINTER(SolveInfo), _VP],
+                     ctypes.c_int),
     "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hhg_last_error": ([], ctypes.c_char_p),

@@ -1,0 +1,721 @@
+// Geometric multigrid on the hierarchy of uniform refinements (the paper's
+// solver, Sec. 5 and 6): one library handle per level of the same macro mesh,
+// P1 prolongation and its transpose between neighbouring levels, damped
+// block-Jacobi smoothing with the scaled operator of every level (coefficient
+// injected from the finest level), an exact solve on the coarsest level and
+// CG preconditioned by one V-cycle.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "hhg_device.h"
+
+struct hhg_mg_s {
+  std::vector<hhg_ctx *> lev;            // coarsest .. finest, owned
+  int coarse_level = 0, fine_level = 0;
+  int device = -1;
+  // restriction weights: 1 / (copies of the slot) at every level above the coarsest
+  std::vector<double *> d_winv;          // [q], q >= 1
+  // coarsest level: unknown nodes (owner slot, all copies)
+  int n_cu = 0;
+  std::vector<int64_t> cu_owner, cu_ptr, cu_slot;
+  int64_t *d_cu_owner = nullptr, *d_cu_ptr = nullptr, *d_cu_slot = nullptr;
+  // host copy of the coarsest operator's inverse is rebuilt per coefficient
+  std::vector<double> dense;
+};
+
+namespace hhg {
+
+int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
+                   void *y, hipStream_t st);
+
+namespace {
+
+constexpr int MG_RED = 512;              // blocks of the dot-product kernel
+
+dim3 grid1(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65535))); }
+
+// (i, j, k) of the macro-local index q (slot order: planes k, rows s = i + j, i)
+__device__ __forceinline__ void local_ijk(int64_t q, int n, int &i, int &j, int &k) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (plane_base(n, mid) <= q) lo = mid; else hi = mid - 1;
+  }
+  k = lo;
+  const int p = (int)(q - plane_base(n, k));
+  const int s = tri_root_dev(p);
+  i = p - s * (s + 1) / 2;
+  j = s - i;
+}
+
+__device__ __forceinline__ int64_t local_slot(int n, int i, int j, int k) {
+  return plane_base(n, k) + (int64_t)(i + j) * (i + j + 1) / 2 + i;
+}
+
+// xf = P xc (or xf += P xc): a fine node that is a coarse node copies it, any
+// other fine node is the midpoint of the coarse lattice edge (F - d)/2 --
+// (F + d)/2, d the lattice direction with F's parity pattern.  Dirichlet
+// slots stay zero.  Grid: (positions, macro).
+template <bool ADD>
+__global__ __launch_bounds__(256) void k_prolong(const MacroInfo *__restrict__ mc,
+                                                 const MacroInfo *__restrict__ mf,
+                                                 const uint8_t *__restrict__ flf,
+                                                 const double *__restrict__ xc, double *__restrict__ xf,
+                                                 int64_t Nc, int64_t Nf) {
+  const int m = blockIdx.y;
+  const int nf = mf[m].n, nc = mc[m].n;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= macro_nodes(nf)) return;
+  const int64_t sf = mf[m].off + q;
+  int I, J, K;
+  local_ijk(q, nf, I, J, K);
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  if (!(flf[sf] & 1)) {
+    const int pi = I & 1, pj = J & 1, pk = K & 1;
+    const int64_t oc = mc[m].off;
+    if (!(pi | pj | pk)) {
+      const int64_t s = oc + local_slot(nc, I >> 1, J >> 1, K >> 1);
+      v0 = xc[s];
+      v1 = xc[Nc + s];
+      v2 = xc[2 * Nc + s];
+    } else {
+      // lattice direction of the parity pattern: (1,0,0) (0,1,0) (0,0,1)
+      // (1,-1,0) (1,0,-1) (0,1,-1) (1,-1,1)
+      const int di = pi;
+      const int dj = pj ? (pi ? -1 : 1) : 0;
+      const int dk = pk ? ((pi ^ pj) ? -1 : 1) : 0;
+      const int64_t sa = oc + local_slot(nc, (I - di) >> 1, (J - dj) >> 1, (K - dk) >> 1);
+      const int64_t sb = oc + local_slot(nc, (I + di) >> 1, (J + dj) >> 1, (K + dk) >> 1);
+      v0 = 0.5 * (xc[sa] + xc[sb]);
+      v1 = 0.5 * (xc[Nc + sa] + xc[Nc + sb]);
+      v2 = 0.5 * (xc[2 * Nc + sa] + xc[2 * Nc + sb]);
+    }
+  }
+  if (ADD) {
+    xf[sf] += v0;
+    xf[Nf + sf] += v1;
+    xf[2 * Nf + sf] += v2;
+  } else {
+    xf[sf] = v0;
+    xf[Nf + sf] = v1;
+    xf[2 * Nf + sf] = v2;
+  }
+}
+
+// Partial rc = P^T rf per coarse copy: the fine node at 2c with weight 1 and
+// the fine midpoints 2c + d of the macro's coarse edges at c with weight 1/2,
+// each divided by the number of copies of the fine node, so that the sum over
+// the coarse copies (k_copy_sum3) counts every fine node once.  Dirichlet
+// coarse slots get zero.
+__global__ __launch_bounds__(256) void k_restrict(const MacroInfo *__restrict__ mc,
+                                                  const MacroInfo *__restrict__ mf,
+                                                  const uint8_t *__restrict__ flc,
+                                                  const double *__restrict__ winv,
+                                                  const double *__restrict__ rf, double *__restrict__ rc,
+                                                  int64_t Nc, int64_t Nf) {
+  const int m = blockIdx.y;
+  const int nf = mf[m].n, nc = mc[m].n;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= macro_nodes(nc)) return;
+  const int64_t sc = mc[m].off + q;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (!(flc[sc] & 1)) {
+    int i, j, k;
+    local_ijk(q, nc, i, j, k);
+    const int64_t of = mf[m].off;
+    {
+      const int64_t s = of + local_slot(nf, 2 * i, 2 * j, 2 * k);
+      const double w = winv[s];
+      s0 = w * rf[s];
+      s1 = w * rf[Nf + s];
+      s2 = w * rf[2 * Nf + s];
+    }
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+      const int a = 2 * i + DIR_I[d], b = 2 * j + DIR_J[d], c = 2 * k + DIR_K[d];
+      if (a < 0 || b < 0 || c < 0 || a + b + c > nf) continue;
+      const int64_t s = of + local_slot(nf, a, b, c);
+      const double w = 0.5 * winv[s];
+      s0 = fma(w, rf[s], s0);
+      s1 = fma(w, rf[Nf + s], s1);
+      s2 = fma(w, rf[2 * Nf + s], s2);
+    }
+  }
+  rc[sc] = s0;
+  rc[Nc + sc] = s1;
+  rc[2 * Nc + sc] = s2;
+}
+
+// Sum over the copies of every interface group, written to all copies.
+__global__ __launch_bounds__(256) void k_copy_sum3(const int64_t *__restrict__ ptr,
+                                                   const int64_t *__restrict__ slots, int64_t ng,
+                                                   double *__restrict__ v, int64_t N) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ptr[g], b = ptr[g + 1];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t q = a; q < b; ++q) {
+      const int64_t s = slots[q];
+      s0 += v[s];
+      s1 += v[N + s];
+      s2 += v[2 * N + s];
+    }
+    for (int64_t q = a; q < b; ++q) {
+      const int64_t s = slots[q];
+      v[s] = s0;
+      v[N + s] = s1;
+      v[2 * N + s] = s2;
+    }
+  }
+}
+
+// kc = fine coefficient at the coarse nodes (fine node 2c of the same macro)
+__global__ __launch_bounds__(256) void k_inject(const MacroInfo *__restrict__ mc,
+                                                const MacroInfo *__restrict__ mf,
+                                                const double *__restrict__ kf, double *__restrict__ kc) {
+  const int m = blockIdx.y;
+  const int nc = mc[m].n, nf = mf[m].n;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= macro_nodes(nc)) return;
+  int i, j, k;
+  local_ijk(q, nc, i, j, k);
+  kc[mc[m].off + q] = kf[mf[m].off + local_slot(nf, 2 * i, 2 * j, 2 * k)];
+}
+
+// x = omega P r (FIRST) or x += omega P r, P the inverse diagonal blocks
+// (xx yy zz xy xz yz, zero at Dirichlet slots)
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ P,
+                                                const double *__restrict__ r, double *__restrict__ x,
+                                                double omega, int64_t N) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const double r0 = r[s], r1 = r[N + s], r2 = r[2 * N + s];
+    const double Pxx = P[s], Pyy = P[N + s], Pzz = P[2 * N + s];
+    const double Pxy = P[3 * N + s], Pxz = P[4 * N + s], Pyz = P[5 * N + s];
+    const double z0 = omega * (Pxx * r0 + Pxy * r1 + Pxz * r2);
+    const double z1 = omega * (Pxy * r0 + Pyy * r1 + Pyz * r2);
+    const double z2 = omega * (Pxz * r0 + Pyz * r1 + Pzz * r2);
+    if (FIRST) {
+      x[s] = z0;
+      x[N + s] = z1;
+      x[2 * N + s] = z2;
+    } else {
+      x[s] += z0;
+      x[N + s] += z1;
+      x[2 * N + s] += z2;
+    }
+  }
+}
+
+__global__ void k_fill0(double *__restrict__ a, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    a[s] = 0.0;
+}
+
+// unit vector of unknown coarse DoF (u, c) at every copy of node u
+__global__ void k_unit(const int64_t *__restrict__ ptr, const int64_t *__restrict__ slots, int u,
+                       int c, double *__restrict__ e, int64_t N) {
+  for (int64_t q = ptr[u] + threadIdx.x; q < ptr[u + 1]; q += blockDim.x) e[c * N + slots[q]] = 1.0;
+}
+
+// column col of the dense coarse operator: y at the owners of all unknown nodes
+__global__ void k_column(const int64_t *__restrict__ owner, int nu, const double *__restrict__ y,
+                         int64_t N, double *__restrict__ A, int col) {
+  const int n3 = 3 * nu;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n3; r += gridDim.x * blockDim.x)
+    A[(int64_t)col * n3 + r] = y[(r % 3) * N + owner[r / 3]];
+}
+
+// x = A^{-1} b on the coarsest level: gather b at the owners, dense product
+// with the inverse (column-major, symmetric), scatter to every copy
+__global__ __launch_bounds__(256) void k_coarse_solve(const int64_t *__restrict__ owner,
+                                                      const int64_t *__restrict__ ptr,
+                                                      const int64_t *__restrict__ slots, int nu,
+                                                      const double *__restrict__ Ainv,
+                                                      const double *__restrict__ b,
+                                                      double *__restrict__ x, int64_t N) {
+  const int n3 = 3 * nu;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n3; r += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < n3; ++c) s = fma(Ainv[(int64_t)c * n3 + r], b[(c % 3) * N + owner[c / 3]], s);
+    const int u = r / 3, comp = r % 3;
+    for (int64_t q = ptr[u]; q < ptr[u + 1]; ++q) x[comp * N + slots[q]] = s;
+  }
+}
+
+// partial sums of (a, b) over unknown owner slots
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a, const double *__restrict__ b,
+                                             const uint8_t *__restrict__ fl, int64_t N,
+                                             double *__restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if ((fl[i] & 3) == 2) s += a[i] * b[i] + a[N + i] * b[N + i] + a[2 * N + i] * b[2 * N + i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// x += alpha p, r -= alpha q
+__global__ void k_axpy2(double *__restrict__ x, const double *__restrict__ p, double *__restrict__ r,
+                        const double *__restrict__ q, double alpha, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    x[s] = fma(alpha, p[s], x[s]);
+    r[s] = fma(-alpha, q[s], r[s]);
+  }
+}
+
+// p = z + beta p
+__global__ void k_xpby(double *__restrict__ p, const double *__restrict__ z, double beta, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    p[s] = fma(beta, p[s], z[s]);
+}
+
+// ----------------------------------------------------------- workspace
+struct MgWork {
+  std::vector<double *> k, P, b, x, r;   // per level
+  double *Ainv = nullptr;                // (3 n_cu)^2, inverse of the coarsest operator
+  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;   // CG vectors (finest)
+  double *part = nullptr;                // MG_RED partial sums
+};
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t layout(const hhg_mg_s *mg, char *base, MgWork *w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+    off += al256(bytes);
+    return p;
+  };
+  const int L = (int)mg->lev.size();
+  MgWork tmp;
+  MgWork &W = w ? *w : tmp;
+  W.k.assign(L, nullptr);
+  W.P.assign(L, nullptr);
+  W.b.assign(L, nullptr);
+  W.x.assign(L, nullptr);
+  W.r.assign(L, nullptr);
+  for (int q = 0; q < L; ++q) {
+    const size_t N = (size_t)mg->lev[q]->n_nodes;
+    W.k[q] = take(8 * N);
+    W.P[q] = take(48 * N);
+    W.b[q] = take(24 * N);
+    W.x[q] = take(24 * N);
+    W.r[q] = take(24 * N);
+  }
+  const size_t n3 = 3 * (size_t)mg->n_cu;
+  W.Ainv = take(8 * n3 * n3);
+  const size_t NF = (size_t)mg->lev.back()->n_nodes;
+  W.pr = take(24 * NF);
+  W.pz = take(24 * NF);
+  W.pp = take(24 * NF);
+  W.pq = take(24 * NF);
+  W.part = take(8 * MG_RED);
+  return off;
+}
+
+int check_mg(const hhg_mg_s *mg) {
+  if (!mg || mg->lev.empty()) return fail(HHG_EINVAL, "null multigrid handle");
+  int dev = -1;
+  HHG_HIP(hipGetDevice(&dev));
+  if (mg->device >= 0 && dev != mg->device)
+    return fail(HHG_EINVAL, "multigrid handle used on another device than the one it was set up on");
+  return HHG_OK;
+}
+
+// device copies of the level metadata (first device call)
+int mg_device(hhg_mg_s *mg) {
+  for (hhg_ctx *h : mg->lev) {
+    const int rc = ensure_device(h);
+    if (rc) return rc;
+  }
+  if (mg->device >= 0) return HHG_OK;
+  HHG_HIP(hipGetDevice(&mg->device));
+  for (size_t q = 1; q < mg->lev.size(); ++q) {
+    hhg_ctx *h = mg->lev[q];
+    std::vector<double> w((size_t)h->n_nodes, 1.0);
+    for (size_t g = 0; g + 1 < h->agrp_ptr.size(); ++g) {
+      const int64_t a = h->agrp_ptr[g], b = h->agrp_ptr[g + 1];
+      for (int64_t s = a; s < b; ++s) w[h->agrp_slot[s]] = 1.0 / (double)(b - a);
+    }
+    double *d = nullptr;
+    HHG_HIP(hipMalloc((void **)&d, w.size() * sizeof(double)));
+    mg->d_winv[q] = d;
+    HHG_HIP(hipMemcpy(d, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  auto up = [](int64_t **dst, const std::vector<int64_t> &v) -> int {
+    HHG_HIP(hipMalloc((void **)dst, std::max<size_t>(1, v.size()) * sizeof(int64_t)));
+    if (!v.empty()) HHG_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    return HHG_OK;
+  };
+  int rc;
+  if ((rc = up(&mg->d_cu_owner, mg->cu_owner))) return rc;
+  if ((rc = up(&mg->d_cu_ptr, mg->cu_ptr))) return rc;
+  if ((rc = up(&mg->d_cu_slot, mg->cu_slot))) return rc;
+  return HHG_OK;
+}
+
+dim3 macro_grid(const hhg_ctx *h) {
+  int maxn = 0;
+  for (const auto &mi : h->minfo) maxn = std::max<int>(maxn, (int)macro_nodes(mi.n));
+  return dim3((unsigned)((maxn + 255) / 256), (unsigned)h->n_macro);
+}
+
+int prolong(hhg_mg_s *mg, int q, const double *xc, double *xf, bool add, hipStream_t st) {
+  hhg_ctx *c = mg->lev[q - 1], *f = mg->lev[q];
+  if (add)
+    hipLaunchKernelGGL(k_prolong<true>, macro_grid(f), dim3(256), 0, st, c->d_minfo, f->d_minfo,
+                       f->d_flags, xc, xf, c->n_nodes, f->n_nodes);
+  else
+    hipLaunchKernelGGL(k_prolong<false>, macro_grid(f), dim3(256), 0, st, c->d_minfo, f->d_minfo,
+                       f->d_flags, xc, xf, c->n_nodes, f->n_nodes);
+  HHG_HIP(hipGetLastError());
+  return HHG_OK;
+}
+
+int restrict_(hhg_mg_s *mg, int q, const double *rf, double *rc, hipStream_t st) {
+  hhg_ctx *c = mg->lev[q - 1], *f = mg->lev[q];
+  hipLaunchKernelGGL(k_restrict, macro_grid(c), dim3(256), 0, st, c->d_minfo, f->d_minfo, c->d_flags,
+                     mg->d_winv[q], rf, rc, c->n_nodes, f->n_nodes);
+  HHG_HIP(hipGetLastError());
+  if (c->n_grp > 0) {
+    hipLaunchKernelGGL(k_copy_sum3, grid1(c->n_grp), dim3(256), 0, st, c->d_grp_ptr, c->d_grp_slot,
+                       c->n_grp, rc, c->n_nodes);
+    HHG_HIP(hipGetLastError());
+  }
+  return HHG_OK;
+}
+
+// x_q = V-cycle applied to b_q (levels q and below)
+int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const double *b, double *x,
+           hipStream_t st) {
+  hhg_ctx *h = mg->lev[q];
+  const int64_t N = h->n_nodes;
+  if (q == 0) {
+    hipLaunchKernelGGL(k_fill0, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
+    if (mg->n_cu > 0)
+      hipLaunchKernelGGL(k_coarse_solve, grid1(3 * mg->n_cu), dim3(256), 0, st, mg->d_cu_owner,
+                         mg->d_cu_ptr, mg->d_cu_slot, mg->n_cu, W.Ainv, b, x, N);
+    HHG_HIP(hipGetLastError());
+    return HHG_OK;
+  }
+  int rc;
+  double *r = W.r[q];
+  auto smooth = [&](bool first) -> int {
+    if (first) {
+      hipLaunchKernelGGL(k_jacobi<true>, grid1(N), dim3(256), 0, st, W.P[q], b, x, o.omega, N);
+    } else {
+      const int rc2 = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[q], r, st);
+      if (rc2) return rc2;
+      hipLaunchKernelGGL(k_jacobi<false>, grid1(N), dim3(256), 0, st, W.P[q], r, x, o.omega, N);
+    }
+    HHG_HIP(hipGetLastError());
+    return HHG_OK;
+  };
+  for (int s = 0; s < o.nu1; ++s)
+    if ((rc = smooth(s == 0))) return rc;
+  if (o.nu1 == 0) hipLaunchKernelGGL(k_fill0, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
+  if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[q], r, st))) return rc;
+  if ((rc = restrict_(mg, q, r, W.b[q - 1], st))) return rc;
+  if ((rc = vcycle(mg, W, o, q - 1, W.b[q - 1], W.x[q - 1], st))) return rc;
+  if ((rc = prolong(mg, q, W.x[q - 1], x, true, st))) return rc;
+  for (int s = 0; s < o.nu2; ++s)
+    if ((rc = smooth(false))) return rc;
+  return HHG_OK;
+}
+
+int dot(hhg_mg_s *mg, const MgWork &W, const double *a, const double *b, double *out,
+        hipStream_t st) {
+  hhg_ctx *h = mg->lev.back();
+  hipLaunchKernelGGL(k_dot, dim3(MG_RED), dim3(256), 0, st, a, b, h->d_flags, h->n_nodes, W.part);
+  HHG_HIP(hipGetLastError());
+  double part[MG_RED];
+  HHG_HIP(hipMemcpyAsync(part, W.part, sizeof(part), hipMemcpyDeviceToHost, st));
+  HHG_HIP(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (int q = 0; q < MG_RED; ++q) s += part[q];
+  *out = s;
+  return HHG_OK;
+}
+
+// Cholesky inverse of a dense SPD matrix (column-major, n x n), in place
+bool spd_inverse(std::vector<double> &A, int n) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int p = 0; p < j; ++p) d -= L[(size_t)p * n + j] * L[(size_t)p * n + j];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[(size_t)j * n + i];
+      for (int p = 0; p < j; ++p) s -= L[(size_t)p * n + i] * L[(size_t)p * n + j];
+      L[(size_t)j * n + i] = s / d;
+    }
+  }
+  // inverse column by column: L L^T x = e_c
+  std::vector<double> y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = i == c ? 1.0 : 0.0;
+      for (int p = 0; p < i; ++p) s -= L[(size_t)p * n + i] * y[p];
+      y[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int p = i + 1; p < n; ++p) s -= L[(size_t)i * n + p] * A[(size_t)c * n + p];
+      A[(size_t)c * n + i] = s / L[(size_t)i * n + i];
+    }
+  }
+  return true;
+}
+
+int check_opts(const hhg_mg_opts *o) {
+  if (!o) return fail(HHG_EINVAL, "null options");
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 64 || o->nu2 > 64)
+    return fail(HHG_EINVAL, "smoothing steps must be 0..64 each, at least one in total");
+  if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(HHG_EINVAL, "omega must lie in (0, 2)");
+  return HHG_OK;
+}
+
+}  // namespace
+}  // namespace hhg
+
+using namespace hhg;
+
+extern "C" {
+
+int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coarse_level,
+                  hhg_mg *out) {
+  if (!mesh || !op || !out || !mesh->level || mesh->n_macro < 1)
+    return fail(HHG_EINVAL, "null argument");
+  *out = nullptr;
+  if (mesh->coupling != HHG_CONFORMING) return fail(HHG_EINVAL, "multigrid needs a conforming mesh");
+  const int L = mesh->level[0];
+  if (coarse_level < 2 || coarse_level > L) return fail(HHG_EINVAL, "coarse level must lie in 2..level");
+  auto *mg = new hhg_mg_s();
+  mg->coarse_level = coarse_level;
+  mg->fine_level = L;
+  std::vector<int32_t> lv((size_t)mesh->n_macro);
+  for (int l = coarse_level; l <= L; ++l) {
+    for (auto &v : lv) v = l;
+    hhg_mesh_desc d = *mesh;
+    d.level = lv.data();
+    hhg_handle h = nullptr;
+    const int rc = hhg_setup_macro(&d, op, &h);
+    if (rc) {
+      hhg_mg_destroy(mg);
+      return rc;
+    }
+    mg->lev.push_back(h);
+  }
+  mg->d_winv.assign(mg->lev.size(), nullptr);
+  // unknown nodes of the coarsest level with all their copies
+  hhg_ctx *c = mg->lev[0];
+  std::vector<int64_t> gid((size_t)c->n_nodes, -1);
+  for (size_t g = 0; g + 1 < c->agrp_ptr.size(); ++g)
+    for (int64_t s = c->agrp_ptr[g]; s < c->agrp_ptr[g + 1]; ++s) gid[c->agrp_slot[s]] = (int64_t)g;
+  mg->cu_ptr.assign(1, 0);
+  for (int64_t s = 0; s < c->n_nodes; ++s) {
+    if ((c->flags[s] & 3) != 2) continue;            // owner copies of unknown nodes
+    mg->cu_owner.push_back(s);
+    if (gid[s] < 0) {
+      mg->cu_slot.push_back(s);
+    } else {
+      for (int64_t q = c->agrp_ptr[gid[s]]; q < c->agrp_ptr[gid[s] + 1]; ++q)
+        mg->cu_slot.push_back(c->agrp_slot[q]);
+    }
+    mg->cu_ptr.push_back((int64_t)mg->cu_slot.size());
+  }
+  mg->n_cu = (int)mg->cu_owner.size();
+  if (mg->n_cu > 512) {
+    hhg_mg_destroy(mg);
+    return fail(HHG_EINVAL, "coarse level too fine for the dense coarse solve (more than 512 unknown nodes)");
+  }
+  *out = mg;
+  return HHG_OK;
+}
+
+int hhg_mg_destroy(hhg_mg mg) {
+  if (!mg) return HHG_OK;
+  for (double *d : mg->d_winv)
+    if (d) (void)hipFree(d);
+  if (mg->d_cu_owner) (void)hipFree(mg->d_cu_owner);
+  if (mg->d_cu_ptr) (void)hipFree(mg->d_cu_ptr);
+  if (mg->d_cu_slot) (void)hipFree(mg->d_cu_slot);
+  for (hhg_ctx *h : mg->lev) hhg_destroy(h);
+  delete mg;
+  return HHG_OK;
+}
+
+int hhg_mg_level(hhg_mg mg, int32_t level, hhg_handle *out) {
+  if (!mg || !out) return fail(HHG_EINVAL, "null argument");
+  if (level < mg->coarse_level || level > mg->fine_level) return fail(HHG_EINVAL, "level out of range");
+  *out = mg->lev[level - mg->coarse_level];
+  return HHG_OK;
+}
+
+int hhg_mg_workspace_bytes(hhg_mg mg, size_t *bytes) {
+  if (!mg || !bytes) return fail(HHG_EINVAL, "null argument");
+  *bytes = layout(mg, nullptr, nullptr);
+  return HHG_OK;
+}
+
+int hhg_mg_prolong(hhg_mg mg, int32_t fine_level, const double *xc, double *xf, void *stream) {
+  int rc = check_mg(mg);
+  if (rc) return rc;
+  if (!xc || !xf) return fail(HHG_EINVAL, "null vector");
+  if (fine_level <= mg->coarse_level || fine_level > mg->fine_level)
+    return fail(HHG_EINVAL, "fine level out of range");
+  if ((rc = mg_device(mg))) return rc;
+  return prolong(mg, fine_level - mg->coarse_level, xc, xf, false, (hipStream_t)stream);
+}
+
+int hhg_mg_restrict(hhg_mg mg, int32_t fine_level, const double *rf, double *rc_, void *stream) {
+  int rc = check_mg(mg);
+  if (rc) return rc;
+  if (!rf || !rc_) return fail(HHG_EINVAL, "null vector");
+  if (fine_level <= mg->coarse_level || fine_level > mg->fine_level)
+    return fail(HHG_EINVAL, "fine level out of range");
+  if ((rc = mg_device(mg))) return rc;
+  return restrict_(mg, fine_level - mg->coarse_level, rf, rc_, (hipStream_t)stream);
+}
+
+int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *stream) {
+  int rc = check_mg(mg);
+  if (rc) return rc;
+  if (!k || !workspace) return fail(HHG_EINVAL, "null argument");
+  if (((uintptr_t)k | (uintptr_t)workspace) & 255) return fail(HHG_EINVAL, "misaligned pointer");
+  if ((rc = mg_device(mg))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  MgWork W;
+  layout(mg, static_cast<char *>(workspace), &W);
+  const int L = (int)mg->lev.size();
+  HHG_HIP(hipMemcpyAsync(W.k[L - 1], k, 8 * (size_t)mg->lev[L - 1]->n_nodes, hipMemcpyDeviceToDevice, st));
+  for (int q = L - 1; q > 0; --q) {
+    hhg_ctx *c = mg->lev[q - 1], *f = mg->lev[q];
+    hipLaunchKernelGGL(k_inject, macro_grid(c), dim3(256), 0, st, c->d_minfo, f->d_minfo, W.k[q],
+                       W.k[q - 1]);
+    HHG_HIP(hipGetLastError());
+  }
+  for (int q = 0; q < L; ++q)
+    if ((rc = hhg_preconditioner(mg->lev[q], HHG_PRECOND_BLOCK_JACOBI, HHG_METHOD_SCALED, W.k[q], W.P[q],
+                                 st)))
+      return rc;
+  // dense coarsest operator, column by column, then its inverse on the host
+  hhg_ctx *c = mg->lev[0];
+  const int n3 = 3 * mg->n_cu;
+  const int64_t N0 = c->n_nodes;
+  for (int col = 0; col < n3; ++col) {
+    hipLaunchKernelGGL(k_fill0, grid1(3 * N0), dim3(256), 0, st, W.b[0], 3 * N0);
+    hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, st, mg->d_cu_ptr, mg->d_cu_slot, col / 3, col % 3,
+                       W.b[0], N0);
+    HHG_HIP(hipGetLastError());
+    if ((rc = apply_internal(c, HHG_F64, HHG_METHOD_SCALED, nullptr, W.b[0], W.k[0], W.x[0], st)))
+      return rc;
+    hipLaunchKernelGGL(k_column, grid1(n3), dim3(256), 0, st, mg->d_cu_owner, mg->n_cu, W.x[0], N0,
+                       W.Ainv, col);
+    HHG_HIP(hipGetLastError());
+  }
+  mg->dense.assign((size_t)n3 * n3, 0.0);
+  if (n3 > 0) {
+    HHG_HIP(hipMemcpyAsync(mg->dense.data(), W.Ainv, mg->dense.size() * 8, hipMemcpyDeviceToHost, st));
+    HHG_HIP(hipStreamSynchronize(st));
+    if (!spd_inverse(mg->dense, n3))
+      return fail(HHG_EBREAKDOWN, "coarsest operator is not symmetric positive definite");
+    HHG_HIP(hipMemcpyAsync(W.Ainv, mg->dense.data(), mg->dense.size() * 8, hipMemcpyHostToDevice, st));
+  }
+  HHG_HIP(hipStreamSynchronize(st));
+  return HHG_OK;
+}
+
+int hhg_mg_vcycle(hhg_mg mg, const hhg_mg_opts *o, const double *r, double *z, void *workspace,
+                  void *stream) {
+  int rc = check_mg(mg);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!r || !z || !workspace) return fail(HHG_EINVAL, "null argument");
+  if (((uintptr_t)r | (uintptr_t)z) & 15 || (uintptr_t)workspace & 255)
+    return fail(HHG_EINVAL, "misaligned pointer");
+  if (r == z) return fail(HHG_EINVAL, "z must not alias r");
+  if ((rc = mg_device(mg))) return rc;
+  MgWork W;
+  layout(mg, static_cast<char *>(workspace), &W);
+  return vcycle(mg, W, *o, (int)mg->lev.size() - 1, r, z, (hipStream_t)stream);
+}
+
+int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, void *workspace,
+                 hhg_solve_info *info, void *stream) {
+  int rc = check_mg(mg);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!b || !x || !workspace || !info) return fail(HHG_EINVAL, "null argument");
+  if (((uintptr_t)b | (uintptr_t)x) & 15 || (uintptr_t)workspace & 255)
+    return fail(HHG_EINVAL, "misaligned pointer");
+  if (!(o->rtol > 0.0) || o->maxit < 1) return fail(HHG_EINVAL, "rtol must be > 0 and maxit >= 1");
+  if ((rc = mg_device(mg))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  MgWork W;
+  layout(mg, static_cast<char *>(workspace), &W);
+  const int F = (int)mg->lev.size() - 1;
+  hhg_ctx *h = mg->lev[F];
+  const int64_t n3 = 3 * h->n_nodes;
+  const auto t0 = std::chrono::steady_clock::now();
+  *info = hhg_solve_info{};
+  double bb = 0.0, rr = 0.0, rho = 0.0, pq = 0.0;
+  if ((rc = dot(mg, W, b, b, &bb, st))) return rc;
+  const double nb = std::sqrt(bb);
+  if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[F], W.pr, st))) return rc;
+  if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
+  int it = 0, status = HHG_OK;
+  if (nb == 0.0 || std::sqrt(rr) <= o->rtol * nb) goto done;
+  if ((rc = vcycle(mg, W, *o, F, W.pr, W.pz, st))) return rc;
+  if ((rc = dot(mg, W, W.pr, W.pz, &rho, st))) return rc;
+  HHG_HIP(hipMemcpyAsync(W.pp, W.pz, 8 * n3, hipMemcpyDeviceToDevice, st));
+  while (true) {
+    if (it >= o->maxit) {
+      status = HHG_ENOCONV;
+      break;
+    }
+    if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, nullptr, W.pp, W.k[F], W.pq, st))) return rc;
+    if ((rc = dot(mg, W, W.pp, W.pq, &pq, st))) return rc;
+    if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rho)) {
+      status = HHG_EBREAKDOWN;
+      break;
+    }
+    const double alpha = rho / pq;
+    hipLaunchKernelGGL(k_axpy2, grid1(n3), dim3(256), 0, st, x, W.pp, W.pr, W.pq, alpha, n3);
+    HHG_HIP(hipGetLastError());
+    ++it;
+    if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
+    if (std::sqrt(rr) <= o->rtol * nb) break;
+    if ((rc = vcycle(mg, W, *o, F, W.pr, W.pz, st))) return rc;
+    double rho_new = 0.0;
+    if ((rc = dot(mg, W, W.pr, W.pz, &rho_new, st))) return rc;
+    hipLaunchKernelGGL(k_xpby, grid1(n3), dim3(256), 0, st, W.pp, W.pz, rho_new / rho, n3);
+    HHG_HIP(hipGetLastError());
+    rho = rho_new;
+  }
+done:
+  // final residual recomputed from x
+  if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[F], W.pr, st))) return rc;
+  if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
+  info->iterations = it;
+  info->outer_iterations = 1;
+  info->status = status;
+  info->rel_residual = nb > 0.0 ? std::sqrt(rr) / nb : 0.0;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status == HHG_ENOCONV) return fail(HHG_ENOCONV, "multigrid CG reached maxit");
+  if (status == HHG_EBREAKDOWN) return fail(HHG_EBREAKDOWN, "multigrid CG breakdown");
+  return HHG_OK;
+}
+
+}  // extern "C"

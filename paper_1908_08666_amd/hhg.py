@@ -44,6 +44,22 @@ def _dev_ptr(t, shape, dtype):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _descriptors(verts, levels, mu0, lam0, mu1, lam1, coupling, dirichlet, corr, khat, iface):
+    """hhg_mesh_desc / hhg_op_desc, plus the arrays they point to."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    M = verts.shape[0]
+    lv = np.ascontiguousarray(np.broadcast_to(np.asarray(levels, dtype=np.int32), (M,)))
+    md = L.MeshDesc(M, verts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    {"conforming": L.HHG_CONFORMING, "independent": L.HHG_INDEPENDENT}[coupling],
+                    {"outer": L.HHG_DIRICHLET_OUTER, "none": L.HHG_DIRICHLET_NONE}[dirichlet])
+    od = L.OpDesc(mu0, lam0, mu1, lam1,
+                  {"physical": L.HHG_CORR_PHYSICAL, "none": L.HHG_CORR_NONE}[corr],
+                  {"patch": L.HHG_KHAT_PATCH, "edge": L.HHG_KHAT_EDGE}[khat],
+                  {"symmetric": L.HHG_IFACE_SYMMETRIC, "rowwise": L.HHG_IFACE_ROWWISE}[iface])
+    return md, od, (verts, lv)
+
+
 class Mesh:
     """Handle of a macro mesh with its operator (``hhg_setup_macro``).
 
@@ -55,23 +71,28 @@ class Mesh:
     def __init__(self, verts, levels, mu0=0.0, lam0=0.0, mu1=0.0, lam1=0.0,
                  coupling="conforming", dirichlet="outer", corr="physical",
                  khat="patch", iface="symmetric"):
-        verts = np.ascontiguousarray(verts, dtype=np.float64)
-        M = verts.shape[0]
-        lv = np.ascontiguousarray(np.broadcast_to(np.asarray(levels, dtype=np.int32), (M,)))
-        md = L.MeshDesc(M, verts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                        lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                        {"conforming": L.HHG_CONFORMING, "independent": L.HHG_INDEPENDENT}[coupling],
-                        {"outer": L.HHG_DIRICHLET_OUTER, "none": L.HHG_DIRICHLET_NONE}[dirichlet])
-        od = L.OpDesc(mu0, lam0, mu1, lam1,
-                      {"physical": L.HHG_CORR_PHYSICAL, "none": L.HHG_CORR_NONE}[corr],
-                      {"patch": L.HHG_KHAT_PATCH, "edge": L.HHG_KHAT_EDGE}[khat],
-                      {"symmetric": L.HHG_IFACE_SYMMETRIC, "rowwise": L.HHG_IFACE_ROWWISE}[iface])
+        md, od, keep = _descriptors(verts, levels, mu0, lam0, mu1, lam1, coupling, dirichlet, corr,
+                                    khat, iface)
         h = ctypes.c_void_p()
         self._lib = L.lib()
         L.check(self._lib.hhg_setup_macro(ctypes.byref(md), ctypes.byref(od), ctypes.byref(h)))
+        self._owner = None
+        self._init_from(h, keep[1])
+
+    @classmethod
+    def _borrowed(cls, h, levels, owner):
+        """A Mesh view of a handle owned by ``owner`` (never destroyed here)."""
+        self = cls.__new__(cls)
+        self._lib = L.lib()
+        self._owner = owner
+        self._init_from(h, levels)
+        return self
+
+    def _init_from(self, h, levels):
         self._h = h
+        M = len(levels)
         self.n_macro = M
-        self.levels = lv.copy()
+        self.levels = np.asarray(levels, dtype=np.int32).copy()
         nn = ctypes.c_int64()
         nu = ctypes.c_int64()
         off = np.zeros(M + 1, dtype=np.int64)
@@ -251,8 +272,135 @@ class Mesh:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.hhg_destroy(self._h)
+            if getattr(self, "_owner", None) is None:
+                self._lib.hhg_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Multigrid:
+    """Geometric multigrid hierarchy (``hhg_mg_create``): levels
+    ``coarse_level..level`` of one conforming macro mesh with the scaled
+    operator, P1 transfers, damped block-Jacobi V-cycles and V-cycle
+    preconditioned CG.  ``meshes[q]`` is a Mesh view of level
+    ``coarse_level + q`` (slot layout of the vectors on that level)."""
+
+    def __init__(self, verts, level, coarse_level=2, mu0=0.0, lam0=0.0, mu1=0.0, lam1=0.0,
+                 dirichlet="outer", corr="physical", khat="patch", iface="symmetric"):
+        md, od, _keep = _descriptors(verts, level, mu0, lam0, mu1, lam1, "conforming", dirichlet,
+                                     corr, khat, iface)
+        self._lib = L.lib()
+        mg = ctypes.c_void_p()
+        L.check(self._lib.hhg_mg_create(ctypes.byref(md), ctypes.byref(od), int(coarse_level),
+                                        ctypes.byref(mg)))
+        self._mg = mg
+        self.coarse_level = int(coarse_level)
+        self.level = int(level)
+        M = np.asarray(verts).shape[0]
+        self.meshes = []
+        for lev in range(self.coarse_level, self.level + 1):
+            h = ctypes.c_void_p()
+            L.check(self._lib.hhg_mg_level(mg, lev, ctypes.byref(h)))
+            self.meshes.append(Mesh._borrowed(h, [lev] * M, self))
+        self._ws = None
+
+    def mesh(self, level) -> "Mesh":
+        return self.meshes[level - self.coarse_level]
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        L.check(self._lib.hhg_mg_workspace_bytes(self._mg, ctypes.byref(n)))
+        return int(n.value)
+
+    def _workspace(self, device):
+        import torch
+        nb = self.workspace_bytes()
+        if self._ws is None or self._ws.numel() < nb + 256 or self._ws.device != device:
+            self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        return ctypes.c_void_p(base + ((-base) % 256))
+
+    @staticmethod
+    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100):
+        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), 0)
+
+    def prolong(self, fine_level, xc, xf=None, stream=None):
+        """xf = P xc (``hhg_mg_prolong``)."""
+        import torch
+        c, f = self.mesh(fine_level - 1), self.mesh(fine_level)
+        if xf is None:
+            xf = torch.empty((3, f.n_nodes), dtype=torch.float64, device=xc.device)
+        L.check(self._lib.hhg_mg_prolong(self._mg, int(fine_level),
+                                          _dev_ptr(xc, (3, c.n_nodes), torch.float64),
+                                          _dev_ptr(xf, (3, f.n_nodes), torch.float64),
+                                          _stream_ptr(stream)))
+        return xf
+
+    def restrict(self, fine_level, rf, rc=None, stream=None):
+        """rc = P^T rf (``hhg_mg_restrict``)."""
+        import torch
+        c, f = self.mesh(fine_level - 1), self.mesh(fine_level)
+        if rc is None:
+            rc = torch.empty((3, c.n_nodes), dtype=torch.float64, device=rf.device)
+        L.check(self._lib.hhg_mg_restrict(self._mg, int(fine_level),
+                                           _dev_ptr(rf, (3, f.n_nodes), torch.float64),
+                                           _dev_ptr(rc, (3, c.n_nodes), torch.float64),
+                                           _stream_ptr(stream)))
+        return rc
+
+    def setup_coefficient(self, k, stream=None):
+        """Inject k (finest level, float64) and build every level's blocks
+        and the coarse inverse (``hhg_mg_setup_coefficient``)."""
+        import torch
+        f = self.meshes[-1]
+        ws = self._workspace(k.device)
+        L.check(self._lib.hhg_mg_setup_coefficient(self._mg, _dev_ptr(k, (f.n_nodes,), torch.float64),
+                                                    ws, _stream_ptr(stream)))
+
+    def vcycle(self, r, z=None, nu1=3, nu2=3, omega=0.7, stream=None):
+        """z = V(r) on the finest level (``hhg_mg_vcycle``)."""
+        import torch
+        f = self.meshes[-1]
+        if z is None:
+            z = torch.empty_like(r)
+        o = self._opts(nu1, nu2, omega)
+        L.check(self._lib.hhg_mg_vcycle(self._mg, ctypes.byref(o), _dev_ptr(r, (3, f.n_nodes), torch.float64),
+                                        _dev_ptr(z, (3, f.n_nodes), torch.float64),
+                                        self._workspace(r.device), _stream_ptr(stream)))
+        return z
+
+    def solve(self, b, x=None, nu1=3, nu2=3, omega=0.7, rtol=1e-8, maxit=100, stream=None,
+              raise_on_status=True):
+        """CG preconditioned by V-cycles (``hhg_mg_solve``); call
+        setup_coefficient first.  Returns (x, info dict)."""
+        import torch
+        f = self.meshes[-1]
+        if x is None:
+            x = torch.zeros((3, f.n_nodes), dtype=torch.float64, device=b.device)
+        o = self._opts(nu1, nu2, omega, rtol, maxit)
+        info = L.SolveInfo()
+        rc = self._lib.hhg_mg_solve(self._mg, ctypes.byref(o), _dev_ptr(b, (3, f.n_nodes), torch.float64),
+                                    _dev_ptr(x, (3, f.n_nodes), torch.float64), self._workspace(b.device),
+                                    ctypes.byref(info), _stream_ptr(stream))
+        out = dict(iterations=info.iterations, status=L.STATUS_NAMES.get(info.status, info.status),
+                   code=rc, rel_residual=info.rel_residual, seconds=info.seconds,
+                   message=(self._lib.hhg_last_error() or b"").decode())
+        if rc != L.HHG_OK and raise_on_status:
+            L.check(rc)
+        return x, out
+
+    def close(self):
+        for m in getattr(self, "meshes", []):
+            m._h = None
+        self.meshes = []
+        if getattr(self, "_mg", None):
+            self._lib.hhg_mg_destroy(self._mg)
+            self._mg = None
 
     def __del__(self):
         try:
