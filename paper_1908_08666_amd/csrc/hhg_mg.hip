@@ -6,6 +6,7 @@
 // CG preconditioned by one V-cycle.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "hhg_device.h"
@@ -662,7 +663,6 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
     return fail(HHG_EINVAL, "misaligned pointer");
   if (!(o->rtol > 0.0) || o->maxit < 1) return fail(HHG_EINVAL, "rtol must be > 0 and maxit >= 1");
   if ((rc = mg_device(mg))) return rc;
-  hipStream_t st = (hipStream_t)stream;
   MgWork W;
   layout(mg, static_cast<char *>(workspace), &W);
   const int F = (int)mg->lev.size() - 1;
@@ -670,6 +670,42 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
   const int64_t n3 = 3 * h->n_nodes;
   const auto t0 = std::chrono::steady_clock::now();
   *info = hhg_solve_info{};
+  // the solve runs on the finest handle's own stream, after the caller's
+  // queued work, and is complete on return
+  HHG_HIP(hipStreamSynchronize((hipStream_t)stream));
+  hipStream_t st = h->solve_stream;
+  // one V-cycle (pr -> pz) captured in a HIP graph and replayed every
+  // iteration (no timing events inside a graph)
+  bool use_graph = std::getenv("HHG_NO_GRAPH") == nullptr;
+  for (hhg_ctx *l : mg->lev) use_graph = use_graph && !l->prof_on;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    HHG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int crc = vcycle(mg, W, *o, F, W.pr, W.pz, st);
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (crc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return crc;
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+  }
+  struct ExecGuard {
+    hipGraphExec_t e;
+    ~ExecGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } guard{exec};
+  auto cycle = [&]() -> int {
+    if (exec) {
+      HHG_HIP(hipGraphLaunch(exec, st));
+      return HHG_OK;
+    }
+    return vcycle(mg, W, *o, F, W.pr, W.pz, st);
+  };
   double bb = 0.0, rr = 0.0, rho = 0.0, pq = 0.0;
   if ((rc = dot(mg, W, b, b, &bb, st))) return rc;
   const double nb = std::sqrt(bb);
@@ -677,7 +713,7 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
   if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
   int it = 0, status = HHG_OK;
   if (nb == 0.0 || std::sqrt(rr) <= o->rtol * nb) goto done;
-  if ((rc = vcycle(mg, W, *o, F, W.pr, W.pz, st))) return rc;
+  if ((rc = cycle())) return rc;
   if ((rc = dot(mg, W, W.pr, W.pz, &rho, st))) return rc;
   HHG_HIP(hipMemcpyAsync(W.pp, W.pz, 8 * n3, hipMemcpyDeviceToDevice, st));
   while (true) {
@@ -697,7 +733,7 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
     ++it;
     if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
     if (std::sqrt(rr) <= o->rtol * nb) break;
-    if ((rc = vcycle(mg, W, *o, F, W.pr, W.pz, st))) return rc;
+    if ((rc = cycle())) return rc;
     double rho_new = 0.0;
     if ((rc = dot(mg, W, W.pr, W.pz, &rho_new, st))) return rc;
     hipLaunchKernelGGL(k_xpby, grid1(n3), dim3(256), 0, st, W.pp, W.pz, rho_new / rho, n3);

@@ -135,3 +135,27 @@ def test_invalid_arguments_rejected():
         mg.vcycle(r, nu1=0, nu2=0)
     with pytest.raises(HHGError):
         mg.vcycle(r, omega=2.5)
+
+
+def test_graph_replayed_cycles_match_eager_cycles(monkeypatch):
+    """hhg_mg_solve replays one captured V-cycle per iteration; without the
+    graph (HHG_NO_GRAPH) the same kernels run eagerly.  Both solves must give
+    the same iterates bit for bit, with eager work between the runs."""
+    mg, orcs, s2n, _ = hierarchy("kuhn6", 4)
+    f = orcs[-1]
+    k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 3), 16, 1.0)
+    mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda())
+    b, b_d = consistent_random(f, s2n[-1], 77)
+    runs = []
+    for eager in (False, True, False):
+        if eager:
+            monkeypatch.setenv("HHG_NO_GRAPH", "1")
+        else:
+            monkeypatch.delenv("HHG_NO_GRAPH", raising=False)
+        x_d, info = mg.solve(b_d, rtol=1e-9, maxit=60)
+        runs.append((x_d.cpu().numpy(), info["iterations"]))
+        _ = mg.vcycle(b_d)          # eager work between the solves
+        torch.cuda.synchronize()
+    for x, it in runs[1:]:
+        assert it == runs[0][1]
+        assert np.array_equal(x, runs[0][0])
