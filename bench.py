@@ -321,11 +321,13 @@ def main():
                     help="also run 256 independent uneven-level problems in one tuned, graph-replayed launch")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned block smoother and compare FCG solves (24 macros, level 6)")
+    ap.add_argument("--elastostatics", action="store_true",
+                    help="also run the paper's manufactured-solution benchmark (V-cycles, levels 3..7)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 buffer 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if not args.quick:
-        args.extra = args.solve = args.batch = args.learned = args.carreau = True
+        args.extra = args.solve = args.batch = args.learned = args.carreau = args.elastostatics = True
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
               f"is not part of this build", file=sys.stderr)
@@ -494,6 +496,22 @@ def main():
         sets64 = sets32 = None
         torch.cuda.empty_cache()
         extra["carreau_cube24"] = carreau_workload(args.carreau_level, dev)
+
+    if args.elastostatics:
+        sets64 = sets32 = None
+        torch.cuda.empty_cache()
+        from paper_1908_08666_amd import elastostatics as ELS
+        variants = {
+            "physical": dict(corr="physical", op_method="scaled", iface="rowwise", method="cycle"),
+            "nodal": dict(corr="physical", op_method="onthefly", iface="rowwise", method="cycle"),
+            "unphysical": dict(corr="none", op_method="scaled", iface="rowwise", method="cycle"),
+            "physical_symmetric_rule": dict(corr="physical", op_method="scaled", iface="symmetric",
+                                            method="cg"),
+        }
+        extra["elastostatics_kuhn6"] = dict(
+            levels=[3, 4, 5, 6, 7], finest=7, paper_levels=[1, 2, 3, 4, 5],
+            load="consistent mass matrix times the interpolated body force",
+            results=ELS.benchmark([3, 4, 5, 6, 7], 7, ms=(1, 8), variants=variants, dev=dev))
 
     cpu = None
     if not args.no_cpu_baseline:

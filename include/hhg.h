@@ -407,8 +407,11 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  *   * smoother: damped block Jacobi x += omega D^-1 (b - A x), D the 3x3
  *     diagonal blocks (the paper smooths with a hybrid Gauss-Seidel);
  *   * coarsest level: exact solve with the inverse of the assembled operator
- *     (at most 512 unknown nodes, e.g. level 2);
- *   * hhg_mg_solve: CG preconditioned by one V(nu1, nu2) cycle per iteration.
+ *     (LU with partial pivoting; at most 512 unknown nodes, e.g. level 2);
+ *   * hhg_mg_solve: CG preconditioned by one V(nu1, nu2) cycle per
+ *     iteration (HHG_MG_CG; needs the symmetric interface rule), or the
+ *     V-cycle iteration x += V(b - A x) the paper uses (HHG_MG_CYCLE; also
+ *     for the row-wise interface rule, whose matrix is not symmetric).
  * Vectors are slot vectors of the level's handle ([3][n_nodes], FP64,
  * consistent, 16-byte aligned); Dirichlet entries are ignored on input and
  * written 0.  The caller owns every vector and the workspace
@@ -419,16 +422,17 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  * (synchronizes) and hhg_mg_solve (synchronizes once per iteration to test
  * convergence).  Errors: HHG_EINVAL (null or misaligned pointer, level out of
  * range, non-conforming mesh, coarse level with more than 512 unknown nodes,
- * nu1 + nu2 < 1, omega outside (0, 2)), HHG_EHIP, HHG_EBREAKDOWN (coarse
- * operator not SPD, or CG breakdown), HHG_ENOCONV (maxit reached; x and info
- * are written).                                                            */
+ * nu1 + nu2 < 1, omega outside (0, 2), unknown method), HHG_EHIP,
+ * HHG_EBREAKDOWN (singular coarse operator, or a breakdown of the solve),
+ * HHG_ENOCONV (maxit reached; x and info are written).                     */
 typedef struct hhg_mg_s *hhg_mg;
+enum hhg_mg_method { HHG_MG_CG = 0, HHG_MG_CYCLE = 1 };
 typedef struct {
   int32_t nu1, nu2;      /* pre- and post-smoothing steps (paper: 3, 3)      */
   double omega;          /* block-Jacobi damping, e.g. 0.7                    */
   double rtol;           /* hhg_mg_solve: ||b - A x|| <= rtol ||b||           */
-  int32_t maxit;         /* hhg_mg_solve: CG iterations allowed               */
-  int32_t pad;
+  int32_t maxit;         /* hhg_mg_solve: iterations (CG steps or cycles)     */
+  int32_t method;        /* hhg_mg_solve: hhg_mg_method                       */
 } hhg_mg_opts;
 int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coarse_level,
                   hhg_mg *out);
@@ -441,8 +445,11 @@ int hhg_mg_prolong(hhg_mg mg, int32_t fine_level, const double *xc, double *xf, 
 /* rc = P^T rf (rc consistent over the copies; Dirichlet entries 0) */
 int hhg_mg_restrict(hhg_mg mg, int32_t fine_level, const double *rf, double *rc, void *stream);
 /* k: FP64 [n_nodes] coefficient of the finest level; injects it, builds the
- * inverse blocks of every level and the coarse inverse in the workspace */
-int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *stream);
+ * inverse blocks of every level and the coarse inverse in the workspace.
+ * method: the operator of every level from here on, HHG_METHOD_SCALED
+ * (physical stencil scaling) or HHG_METHOD_ONTHEFLY (nodal integration) */
+int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *workspace,
+                             void *stream);
 /* z = V(r): one V(nu1, nu2) cycle on the finest level from z = 0 */
 int hhg_mg_vcycle(hhg_mg mg, const hhg_mg_opts *o, const double *r, double *z, void *workspace,
                   void *stream);

@@ -56,7 +56,10 @@ HHG_SAMPLE_BYTES = 128
 
 class MgOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
-                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+HHG_MG_CG, HHG_MG_CYCLE = 0, 1
 
 
 class TrainOpts(ctypes.Structure):
@@ -129,7 +132,7 @@ SIGNATURES = {
     "hhg_mg_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hhg_mg_prolong": ([_VP, _I32, _VP, _VP, _VP], ctypes.c_int),
     "hhg_mg_restrict": ([_VP, _I32, _VP, _VP, _VP], ctypes.c_int),
-    "hhg_mg_setup_coefficient": ([_VP, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_setup_coefficient": ([_VP, _I32, _VP, _VP, _VP], ctypes.c_int),
     "hhg_mg_vcycle": ([_VP, ctypes.POINTER(MgOpts), _VP, _VP, _VP, _VP], ctypes.c_int),
     "hhg_mg_solve": ([_VP, ctypes.POINTER(MgOpts), _VP, _VP, _VP, ctypes.POINTER(SolveInfo), _VP],
                      ctypes.c_int),
@@ -146,6 +149,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    # torch's HIP runtime is brought up first: when libhhg.so was loaded
+    # before it, the library's first HIP call found no device
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in SIGNATURES.items():
         fn = getattr(L, name)

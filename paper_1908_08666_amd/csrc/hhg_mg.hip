@@ -15,6 +15,7 @@ struct hhg_mg_s {
   std::vector<hhg_ctx *> lev;            // coarsest .. finest, owned
   int coarse_level = 0, fine_level = 0;
   int device = -1;
+  int method = HHG_METHOD_SCALED;        // operator of the last coefficient setup
   // restriction weights: 1 / (copies of the slot) at every level above the coarsest
   std::vector<double *> d_winv;          // [q], q >= 1
   // coarsest level: unknown nodes (owner slot, all copies)
@@ -414,7 +415,7 @@ int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const dou
     if (first) {
       hipLaunchKernelGGL(k_jacobi<true>, grid1(N), dim3(256), 0, st, W.P[q], b, x, o.omega, N);
     } else {
-      const int rc2 = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[q], r, st);
+      const int rc2 = apply_internal(h, HHG_F64, mg->method, b, x, W.k[q], r, st);
       if (rc2) return rc2;
       hipLaunchKernelGGL(k_jacobi<false>, grid1(N), dim3(256), 0, st, W.P[q], r, x, o.omega, N);
     }
@@ -424,7 +425,7 @@ int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const dou
   for (int s = 0; s < o.nu1; ++s)
     if ((rc = smooth(s == 0))) return rc;
   if (o.nu1 == 0) hipLaunchKernelGGL(k_fill0, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
-  if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[q], r, st))) return rc;
+  if ((rc = apply_internal(h, HHG_F64, mg->method, b, x, W.k[q], r, st))) return rc;
   if ((rc = restrict_(mg, q, r, W.b[q - 1], st))) return rc;
   if ((rc = vcycle(mg, W, o, q - 1, W.b[q - 1], W.x[q - 1], st))) return rc;
   if ((rc = prolong(mg, q, W.x[q - 1], x, true, st))) return rc;
@@ -447,34 +448,47 @@ int dot(hhg_mg_s *mg, const MgWork &W, const double *a, const double *b, double 
   return HHG_OK;
 }
 
-// Cholesky inverse of a dense SPD matrix (column-major, n x n), in place
-bool spd_inverse(std::vector<double> &A, int n) {
-  std::vector<double> L((size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    double d = A[(size_t)j * n + j];
-    for (int p = 0; p < j; ++p) d -= L[(size_t)p * n + j] * L[(size_t)p * n + j];
-    if (!(d > 0.0)) return false;
-    d = std::sqrt(d);
-    L[(size_t)j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double s = A[(size_t)j * n + i];
-      for (int p = 0; p < j; ++p) s -= L[(size_t)p * n + i] * L[(size_t)p * n + j];
-      L[(size_t)j * n + i] = s / d;
+// Inverse of a dense matrix (column-major, n x n) in place by LU with
+// partial pivoting; false if a pivot vanishes.  The coarsest operator is
+// symmetric only under the symmetric interface rule.
+bool dense_inverse(std::vector<double> &A, int n) {
+  std::vector<double> LU(A);
+  std::vector<int> piv(n);
+  auto at = [&](int r, int c) -> double & { return LU[(size_t)c * n + r]; };
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(at(r, c)) > std::fabs(at(p, c))) p = r;
+    if (!(std::fabs(at(p, c)) > 1e-14 * amax)) return false;
+    piv[c] = p;
+    if (p != c)
+      for (int q = 0; q < n; ++q) std::swap(at(c, q), at(p, q));
+    const double d = at(c, c);
+    for (int r = c + 1; r < n; ++r) {
+      const double l = at(r, c) / d;
+      at(r, c) = l;
+      if (l != 0.0)
+        for (int q = c + 1; q < n; ++q) at(r, q) -= l * at(c, q);
     }
   }
-  // inverse column by column: L L^T x = e_c
+  // solve LU x = P e_c column by column
   std::vector<double> y(n);
   for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) y[i] = i == c ? 1.0 : 0.0;
+    for (int i = 0; i < n; ++i) std::swap(y[i], y[piv[i]]);
     for (int i = 0; i < n; ++i) {
-      double s = i == c ? 1.0 : 0.0;
-      for (int p = 0; p < i; ++p) s -= L[(size_t)p * n + i] * y[p];
-      y[i] = s / L[(size_t)i * n + i];
+      double s = y[i];
+      for (int q = 0; q < i; ++q) s -= at(i, q) * y[q];
+      y[i] = s;
     }
     for (int i = n - 1; i >= 0; --i) {
       double s = y[i];
-      for (int p = i + 1; p < n; ++p) s -= L[(size_t)i * n + p] * A[(size_t)c * n + p];
-      A[(size_t)c * n + i] = s / L[(size_t)i * n + i];
+      for (int q = i + 1; q < n; ++q) s -= at(i, q) * y[q];
+      y[i] = s / at(i, i);
     }
+    for (int i = 0; i < n; ++i) A[(size_t)c * n + i] = y[i];
   }
   return true;
 }
@@ -484,6 +498,8 @@ int check_opts(const hhg_mg_opts *o) {
   if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 64 || o->nu2 > 64)
     return fail(HHG_EINVAL, "smoothing steps must be 0..64 each, at least one in total");
   if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(HHG_EINVAL, "omega must lie in (0, 2)");
+  if (o->method != HHG_MG_CG && o->method != HHG_MG_CYCLE)
+    return fail(HHG_EINVAL, "unknown multigrid solve method");
   return HHG_OK;
 }
 
@@ -590,10 +606,14 @@ int hhg_mg_restrict(hhg_mg mg, int32_t fine_level, const double *rf, double *rc_
   return restrict_(mg, fine_level - mg->coarse_level, rf, rc_, (hipStream_t)stream);
 }
 
-int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *stream) {
+int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *workspace,
+                             void *stream) {
   int rc = check_mg(mg);
   if (rc) return rc;
   if (!k || !workspace) return fail(HHG_EINVAL, "null argument");
+  if (method != HHG_METHOD_SCALED && method != HHG_METHOD_ONTHEFLY)
+    return fail(HHG_EINVAL, "unknown operator method");
+  mg->method = method;
   if (((uintptr_t)k | (uintptr_t)workspace) & 255) return fail(HHG_EINVAL, "misaligned pointer");
   if ((rc = mg_device(mg))) return rc;
   hipStream_t st = (hipStream_t)stream;
@@ -608,7 +628,7 @@ int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *
     HHG_HIP(hipGetLastError());
   }
   for (int q = 0; q < L; ++q)
-    if ((rc = hhg_preconditioner(mg->lev[q], HHG_PRECOND_BLOCK_JACOBI, HHG_METHOD_SCALED, W.k[q], W.P[q],
+    if ((rc = hhg_preconditioner(mg->lev[q], HHG_PRECOND_BLOCK_JACOBI, method, W.k[q], W.P[q],
                                  st)))
       return rc;
   // dense coarsest operator, column by column, then its inverse on the host
@@ -620,7 +640,7 @@ int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *
     hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, st, mg->d_cu_ptr, mg->d_cu_slot, col / 3, col % 3,
                        W.b[0], N0);
     HHG_HIP(hipGetLastError());
-    if ((rc = apply_internal(c, HHG_F64, HHG_METHOD_SCALED, nullptr, W.b[0], W.k[0], W.x[0], st)))
+    if ((rc = apply_internal(c, HHG_F64, method, nullptr, W.b[0], W.k[0], W.x[0], st)))
       return rc;
     hipLaunchKernelGGL(k_column, grid1(n3), dim3(256), 0, st, mg->d_cu_owner, mg->n_cu, W.x[0], N0,
                        W.Ainv, col);
@@ -630,8 +650,8 @@ int hhg_mg_setup_coefficient(hhg_mg mg, const double *k, void *workspace, void *
   if (n3 > 0) {
     HHG_HIP(hipMemcpyAsync(mg->dense.data(), W.Ainv, mg->dense.size() * 8, hipMemcpyDeviceToHost, st));
     HHG_HIP(hipStreamSynchronize(st));
-    if (!spd_inverse(mg->dense, n3))
-      return fail(HHG_EBREAKDOWN, "coarsest operator is not symmetric positive definite");
+    if (!dense_inverse(mg->dense, n3))
+      return fail(HHG_EBREAKDOWN, "coarsest operator is singular");
     HHG_HIP(hipMemcpyAsync(W.Ainv, mg->dense.data(), mg->dense.size() * 8, hipMemcpyHostToDevice, st));
   }
   HHG_HIP(hipStreamSynchronize(st));
@@ -709,10 +729,31 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
   double bb = 0.0, rr = 0.0, rho = 0.0, pq = 0.0;
   if ((rc = dot(mg, W, b, b, &bb, st))) return rc;
   const double nb = std::sqrt(bb);
-  if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[F], W.pr, st))) return rc;
+  if ((rc = apply_internal(h, HHG_F64, mg->method, b, x, W.k[F], W.pr, st))) return rc;
   if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
   int it = 0, status = HHG_OK;
   if (nb == 0.0 || std::sqrt(rr) <= o->rtol * nb) goto done;
+  if (o->method == HHG_MG_CYCLE) {
+    // stationary iteration x += V(b - A x)
+    while (true) {
+      if (it >= o->maxit) {
+        status = HHG_ENOCONV;
+        break;
+      }
+      if ((rc = cycle())) return rc;
+      hipLaunchKernelGGL(k_xpby, grid1(n3), dim3(256), 0, st, x, W.pz, 1.0, n3);
+      HHG_HIP(hipGetLastError());
+      ++it;
+      if ((rc = apply_internal(h, HHG_F64, mg->method, b, x, W.k[F], W.pr, st))) return rc;
+      if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
+      if (!std::isfinite(rr)) {
+        status = HHG_EBREAKDOWN;
+        break;
+      }
+      if (std::sqrt(rr) <= o->rtol * nb) break;
+    }
+    goto done;
+  }
   if ((rc = cycle())) return rc;
   if ((rc = dot(mg, W, W.pr, W.pz, &rho, st))) return rc;
   HHG_HIP(hipMemcpyAsync(W.pp, W.pz, 8 * n3, hipMemcpyDeviceToDevice, st));
@@ -721,7 +762,7 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
       status = HHG_ENOCONV;
       break;
     }
-    if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, nullptr, W.pp, W.k[F], W.pq, st))) return rc;
+    if ((rc = apply_internal(h, HHG_F64, mg->method, nullptr, W.pp, W.k[F], W.pq, st))) return rc;
     if ((rc = dot(mg, W, W.pp, W.pq, &pq, st))) return rc;
     if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rho)) {
       status = HHG_EBREAKDOWN;
@@ -742,15 +783,15 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
   }
 done:
   // final residual recomputed from x
-  if ((rc = apply_internal(h, HHG_F64, HHG_METHOD_SCALED, b, x, W.k[F], W.pr, st))) return rc;
+  if ((rc = apply_internal(h, HHG_F64, mg->method, b, x, W.k[F], W.pr, st))) return rc;
   if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
   info->iterations = it;
   info->outer_iterations = 1;
   info->status = status;
   info->rel_residual = nb > 0.0 ? std::sqrt(rr) / nb : 0.0;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (status == HHG_ENOCONV) return fail(HHG_ENOCONV, "multigrid CG reached maxit");
-  if (status == HHG_EBREAKDOWN) return fail(HHG_EBREAKDOWN, "multigrid CG breakdown");
+  if (status == HHG_ENOCONV) return fail(HHG_ENOCONV, "multigrid solve reached maxit");
+  if (status == HHG_EBREAKDOWN) return fail(HHG_EBREAKDOWN, "multigrid solve breakdown");
   return HHG_OK;
 }
 

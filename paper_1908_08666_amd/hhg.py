@@ -326,8 +326,9 @@ class Multigrid:
         return ctypes.c_void_p(base + ((-base) % 256))
 
     @staticmethod
-    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100):
-        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), 0)
+    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100, method="cg"):
+        m = {"cg": L.HHG_MG_CG, "cycle": L.HHG_MG_CYCLE}[method]
+        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), m)
 
     def prolong(self, fine_level, xc, xf=None, stream=None):
         """xf = P xc (``hhg_mg_prolong``)."""
@@ -353,13 +354,15 @@ class Multigrid:
                                            _stream_ptr(stream)))
         return rc
 
-    def setup_coefficient(self, k, stream=None):
+    def setup_coefficient(self, k, method="scaled", stream=None):
         """Inject k (finest level, float64) and build every level's blocks
-        and the coarse inverse (``hhg_mg_setup_coefficient``)."""
+        and the coarse inverse for the scaled or the nodal-integration
+        ("onthefly") operator (``hhg_mg_setup_coefficient``)."""
         import torch
         f = self.meshes[-1]
         ws = self._workspace(k.device)
-        L.check(self._lib.hhg_mg_setup_coefficient(self._mg, _dev_ptr(k, (f.n_nodes,), torch.float64),
+        m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
+        L.check(self._lib.hhg_mg_setup_coefficient(self._mg, m, _dev_ptr(k, (f.n_nodes,), torch.float64),
                                                     ws, _stream_ptr(stream)))
 
     def vcycle(self, r, z=None, nu1=3, nu2=3, omega=0.7, stream=None):
@@ -374,15 +377,16 @@ class Multigrid:
                                         self._workspace(r.device), _stream_ptr(stream)))
         return z
 
-    def solve(self, b, x=None, nu1=3, nu2=3, omega=0.7, rtol=1e-8, maxit=100, stream=None,
-              raise_on_status=True):
-        """CG preconditioned by V-cycles (``hhg_mg_solve``); call
-        setup_coefficient first.  Returns (x, info dict)."""
+    def solve(self, b, x=None, nu1=3, nu2=3, omega=0.7, rtol=1e-8, maxit=100, method="cg",
+              stream=None, raise_on_status=True):
+        """A x = b by V-cycle-preconditioned CG (method "cg") or the V-cycle
+        iteration (method "cycle") (``hhg_mg_solve``); call setup_coefficient
+        first.  Returns (x, info dict)."""
         import torch
         f = self.meshes[-1]
         if x is None:
             x = torch.zeros((3, f.n_nodes), dtype=torch.float64, device=b.device)
-        o = self._opts(nu1, nu2, omega, rtol, maxit)
+        o = self._opts(nu1, nu2, omega, rtol, maxit, method)
         info = L.SolveInfo()
         rc = self._lib.hhg_mg_solve(self._mg, ctypes.byref(o), _dev_ptr(b, (3, f.n_nodes), torch.float64),
                                     _dev_ptr(x, (3, f.n_nodes), torch.float64), self._workspace(b.device),

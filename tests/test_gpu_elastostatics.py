@@ -1,0 +1,35 @@
+"""The paper's linear elastostatics benchmark (Sec. 5.1.2) on the GPU.
+
+Manufactured solution on the unit cube, Young's modulus E = cos(m pi x y z) + 2,
+solved by V-cycles on the 6-macro Kuhn cube at levels 3..5 (the paper's
+levels 1..3) with errors measured on level 6.  Checks: second-order
+convergence of the physically scaled operator (row-wise interface rule, as
+the paper runs it), errors within a factor 2 of the values the paper prints
+(tests/golden/elastostatics_errors.json, its Table tab:benchmarkphysical_and_
+unphysical), and the stagnation of the unphysical scaling."""
+import json
+import os
+
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "elastostatics_errors.json")))
+
+
+def test_physical_scaling_converges_at_second_order():
+    from paper_1908_08666_amd import elastostatics as E
+    variants = {"physical": dict(corr="physical", op_method="scaled"),
+                "unphysical": dict(corr="none", op_method="scaled")}
+    res = E.benchmark([3, 4, 5], 6, ms=(1,), variants=variants)
+    phys, unph = res["m1_physical"], res["m1_unphysical"]
+    for r in phys + unph:
+        print(f"  {r}", flush=True)
+        assert r["status"] == "HHG_OK" and r["iterations"] <= 40
+    assert phys[1]["eoc"] >= 1.8 and phys[2]["eoc"] >= 1.7
+    for q, paper in enumerate(GOLD["physical"]["1"][:2]):
+        assert 0.5 <= phys[q]["error"] / paper <= 2.0, (phys[q]["error"], paper)
+    # without the correction the error stalls at the scaling's inconsistency
+    assert unph[2]["error"] >= 5.0 * phys[2]["error"]
+    assert unph[2]["eoc"] <= 0.5

@@ -19,6 +19,10 @@ Newtonian operators on uniformly refined macro-tetrahedra, Sec. 2 and Sec. 5):
                  level 7, Carreau viscosity of a seeded smooth velocity field.
 * ``batch256``   256 independent unit macro-tets, levels uniform in 3..6, each
                  with its own Fourier coefficient field.
+* ``elastostatics_*``  the paper's linear elastostatics benchmark (Sec. 5.1.2):
+                 Young's modulus E = cos(m pi x y z) + 2, manufactured solution
+                 u*, body force f = -div sigma(u*) (PDE data, derived exactly
+                 by automatic differentiation).
 """
 from __future__ import annotations
 
@@ -226,3 +230,51 @@ def eform_weights(nu: float = 0.34):
 
 
 CARREAU_DEFAULT = dict(eta0=1.0, eta_inf=1e-3, kappa=1.0, r=-0.25)
+
+
+# ------------------------------------------------ linear elastostatics benchmark
+def elastostatics_modulus(xyz: np.ndarray, m: int) -> np.ndarray:
+    """Young's modulus E(x, y, z) = cos(m pi x y z) + 2 (Sec. 5.1.2)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.cos(m * np.pi * x * y * z) + 2.0
+
+
+def _u_star_t(X):
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    d = x * y * z + 1.0
+    import torch
+    return torch.stack([(x ** 3 * y + z ** 2) / d, (x ** 4 * y + 2.0 * z) / d,
+                        (3.0 * x + y * z ** 3) / d], dim=1)
+
+
+def elastostatics_solution(xyz: np.ndarray) -> np.ndarray:
+    """Manufactured solution u*(x, y, z) of Sec. 5.1.2, (n, 3)."""
+    import torch
+    return _u_star_t(torch.from_numpy(np.asarray(xyz, dtype=np.float64))).numpy()
+
+
+def elastostatics_force(xyz: np.ndarray, m: int, nu: float = 0.34, chunk: int = 1 << 18) -> np.ndarray:
+    """Body force f = -div sigma(u*) with sigma = E (eps/(1+nu) +
+    nu/((1+nu)(1-2nu)) tr(eps) I) (eq. stressE), (n, 3).  Derivatives are
+    taken by automatic differentiation in FP64 (exact up to rounding)."""
+    import torch
+    a = 1.0 / (1.0 + nu)
+    b = nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    out = np.empty((xyz.shape[0], 3))
+    for s in range(0, xyz.shape[0], chunk):
+        X = torch.tensor(np.asarray(xyz[s:s + chunk], dtype=np.float64), requires_grad=True)
+        u = _u_star_t(X)
+        # grad u: G[:, c, d] = d u_c / d x_d
+        G = torch.stack([torch.autograd.grad(u[:, c].sum(), X, create_graph=True)[0] for c in range(3)], dim=1)
+        eps = 0.5 * (G + G.transpose(1, 2))
+        tr = eps[:, 0, 0] + eps[:, 1, 1] + eps[:, 2, 2]
+        E = torch.cos(m * np.pi * X[:, 0] * X[:, 1] * X[:, 2]) + 2.0
+        sig = E[:, None, None] * (a * eps + b * tr[:, None, None] * torch.eye(3, dtype=X.dtype))
+        f = torch.zeros((X.shape[0], 3), dtype=X.dtype)
+        for c in range(3):
+            for d in range(3):
+                g = torch.autograd.grad(sig[:, c, d].sum(), X, retain_graph=True)[0]
+                f[:, c] -= g[:, d]
+        out[s:s + chunk] = f.detach().numpy()
+    return out
+
