@@ -417,12 +417,14 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  * written 0.  The caller owns every vector and the workspace
  * (hhg_mg_workspace_bytes, 256-byte aligned), which holds the per-level
  * coefficients, inverse blocks, vectors and the coarse inverse between
- * hhg_mg_setup_coefficient and the cycles that use them.  Calls are
+ * hhg_mg_setup_coefficient and the cycles that use them (cycles and solves
+ * accept only the workspace of the last coefficient setup).  Calls are
  * asynchronous on the stream except hhg_mg_create, hhg_mg_setup_coefficient
  * (synchronizes) and hhg_mg_solve (synchronizes once per iteration to test
  * convergence).  Errors: HHG_EINVAL (null or misaligned pointer, level out of
- * range, non-conforming mesh, coarse level with more than 512 unknown nodes,
- * nu1 + nu2 < 1, omega outside (0, 2), unknown method), HHG_EHIP,
+ * range, mixed levels, non-conforming mesh, a workspace without coefficient
+ * setup, coarse level with more than 512 unknown nodes, nu1 + nu2 < 1,
+ * omega outside (0, 2), unknown method), HHG_EHIP,
  * HHG_EBREAKDOWN (singular coarse operator, or a breakdown of the solve),
  * HHG_ENOCONV (maxit reached; x and info are written).                     */
 typedef struct hhg_mg_s *hhg_mg;

@@ -16,6 +16,7 @@ struct hhg_mg_s {
   int coarse_level = 0, fine_level = 0;
   int device = -1;
   int method = HHG_METHOD_SCALED;        // operator of the last coefficient setup
+  const void *ready = nullptr;           // workspace of the last coefficient setup
   // restriction weights: 1 / (copies of the slot) at every level above the coarsest
   std::vector<double *> d_winv;          // [q], q >= 1
   // coarsest level: unknown nodes (owner slot, all copies)
@@ -517,6 +518,8 @@ int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coar
   *out = nullptr;
   if (mesh->coupling != HHG_CONFORMING) return fail(HHG_EINVAL, "multigrid needs a conforming mesh");
   const int L = mesh->level[0];
+  for (int m = 1; m < mesh->n_macro; ++m)
+    if (mesh->level[m] != L) return fail(HHG_EINVAL, "multigrid needs one common level");
   if (coarse_level < 2 || coarse_level > L) return fail(HHG_EINVAL, "coarse level must lie in 2..level");
   auto *mg = new hhg_mg_s();
   mg->coarse_level = coarse_level;
@@ -614,6 +617,7 @@ int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *w
   if (method != HHG_METHOD_SCALED && method != HHG_METHOD_ONTHEFLY)
     return fail(HHG_EINVAL, "unknown operator method");
   mg->method = method;
+  mg->ready = nullptr;
   if (((uintptr_t)k | (uintptr_t)workspace) & 255) return fail(HHG_EINVAL, "misaligned pointer");
   if ((rc = mg_device(mg))) return rc;
   hipStream_t st = (hipStream_t)stream;
@@ -655,6 +659,7 @@ int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *w
     HHG_HIP(hipMemcpyAsync(W.Ainv, mg->dense.data(), mg->dense.size() * 8, hipMemcpyHostToDevice, st));
   }
   HHG_HIP(hipStreamSynchronize(st));
+  mg->ready = workspace;
   return HHG_OK;
 }
 
@@ -667,6 +672,8 @@ int hhg_mg_vcycle(hhg_mg mg, const hhg_mg_opts *o, const double *r, double *z, v
   if (((uintptr_t)r | (uintptr_t)z) & 15 || (uintptr_t)workspace & 255)
     return fail(HHG_EINVAL, "misaligned pointer");
   if (r == z) return fail(HHG_EINVAL, "z must not alias r");
+  if (workspace != mg->ready)
+    return fail(HHG_EINVAL, "call hhg_mg_setup_coefficient with this workspace first");
   if ((rc = mg_device(mg))) return rc;
   MgWork W;
   layout(mg, static_cast<char *>(workspace), &W);
@@ -682,6 +689,8 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
   if (((uintptr_t)b | (uintptr_t)x) & 15 || (uintptr_t)workspace & 255)
     return fail(HHG_EINVAL, "misaligned pointer");
   if (!(o->rtol > 0.0) || o->maxit < 1) return fail(HHG_EINVAL, "rtol must be > 0 and maxit >= 1");
+  if (workspace != mg->ready)
+    return fail(HHG_EINVAL, "call hhg_mg_setup_coefficient with this workspace first");
   if ((rc = mg_device(mg))) return rc;
   MgWork W;
   layout(mg, static_cast<char *>(workspace), &W);

@@ -159,3 +159,23 @@ def test_graph_replayed_cycles_match_eager_cycles(monkeypatch):
     for x, it in runs[1:]:
         assert it == runs[0][1]
         assert np.array_equal(x, runs[0][0])
+
+
+def test_cycles_need_the_workspace_of_the_coefficient_setup():
+    from paper_1908_08666_amd._lib import HHGError
+    mg, orcs, s2n, _ = hierarchy("kuhn6", 4)
+    f = orcs[-1]
+    k = torch.from_numpy(scatter(W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 0), 16, 1.0),
+                                 s2n[-1])).cuda()
+    mg.setup_coefficient(k)
+    r = torch.ones((3, mg.meshes[-1].n_nodes), dtype=torch.float64, device="cuda")
+    mg.vcycle(r)                      # the workspace of the setup: accepted
+    old = mg._ws                      # kept alive, so the fresh workspace gets another address
+    mg._ws = None                     # a fresh workspace without coefficient setup
+    with pytest.raises(HHGError):
+        mg.vcycle(r)
+    with pytest.raises(HHGError):
+        mg.solve(r)
+    assert mg._ws.data_ptr() != old.data_ptr()
+    mg.setup_coefficient(k)           # set up again on the new workspace
+    mg.vcycle(r)
