@@ -26,13 +26,13 @@ EFORM = dict(mu1=MU, lam1=LAM)
 _cache = {}
 
 
-def hierarchy(name, level, coarse=2, op=None):
+def hierarchy(name, level, coarse=2, op=None, **variant):
     from paper_1908_08666_amd import Multigrid
     op = EFORM if op is None else op
     V = {"kuhn6": W.kuhn6(), "cube24": W.cube24()}[name]
-    key = (name, level, coarse, tuple(sorted(op.items())))
+    key = (name, level, coarse, tuple(sorted(op.items())), tuple(sorted(variant.items())))
     if key not in _cache:
-        mg = Multigrid(V, level, coarse, **op)
+        mg = Multigrid(V, level, coarse, **op, **variant)
         orcs = [MacroMesh(V, lev) for lev in range(coarse, level + 1)]
         s2n = [slot_to_node(m, o) for m, o in zip(mg.meshes, orcs)]
         _cache[key] = (mg, orcs, s2n, V)
@@ -179,3 +179,33 @@ def test_cycles_need_the_workspace_of_the_coefficient_setup():
     assert mg._ws.data_ptr() != old.data_ptr()
     mg.setup_coefficient(k)           # set up again on the new workspace
     mg.vcycle(r)
+
+
+@pytest.mark.parametrize("method,iface,corr", [("onthefly", "symmetric", "physical"),
+                                               ("scaled", "rowwise", "physical"),
+                                               ("scaled", "symmetric", "none")])
+def test_vcycle_variants_match_oracle(method, iface, corr):
+    """V-cycles for the nodal-integration operator, the row-wise interface
+    rule (a non-symmetric matrix: the coarse solve pivots) and the
+    unphysical scaling against the oracle's cycle of the same operator; for
+    the row-wise rule also the V-cycle iteration against the direct solve."""
+    mg, orcs, s2n, V = hierarchy("kuhn6", 4, iface=iface, corr=corr)
+    f = orcs[-1]
+    k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 5), 16, 1.0)
+    H = MG.Hierarchy(V, mg.coarse_level, 4, k, EFORM,
+                     method="nodal" if method == "onthefly" else "scaled",
+                     **({} if method == "onthefly" else dict(iface=iface, corr=corr)))
+    mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda(), method=method)
+    r, r_d = consistent_random(f, s2n[-1], 60)
+    z = gather_consistent(mg.vcycle(r_d).cpu().numpy(), s2n[-1], f.n_nodes)
+    ref = node_vec(MG.vcycle(H, dof_vec(r, f)), f)
+    err = rel_err(z[f.unknown], ref[f.unknown])
+    print(f"  {method} {iface} {corr}: V-cycle rel err {err:.2e}", flush=True)
+    assert err <= 1e-10
+    if iface == "rowwise":
+        x_d, info = mg.solve(r_d, rtol=1e-11, maxit=80, method="cycle")
+        assert info["status"] == "HHG_OK"
+        x = gather_consistent(x_d.cpu().numpy(), s2n[-1], f.n_nodes)
+        xs = node_vec(spla.spsolve(H.A[-1].tocsc(), dof_vec(r, f)), f)
+        assert rel_err(x[f.unknown], xs[f.unknown]) <= 1e-8
+
