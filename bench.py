@@ -97,11 +97,11 @@ def cpu_baseline(level, rows_sample, seed=0):
                        f"single-threaded NumPy")
 
 
-def mg_solve(verts, level, op, k, b, coarse=2, rtol=1e-8, maxit=100):
+def mg_solve(verts, level, op, k, b, coarse=2, rtol=1e-8, maxit=100, precision="f64"):
     """V(3,3)-cycle preconditioned CG on the hierarchy coarse..level (damped
-    block Jacobi, omega 0.7, exact coarsest solve): coefficient setup time
-    (injection, inverse blocks of every level, coarse inverse) and solve time
-    of a second, warm run."""
+    block Jacobi, omega 0.7, exact coarsest solve; cycles in FP64 or FP32,
+    CG in FP64): coefficient setup time (injection, inverse blocks of every
+    level, coarse inverse) and solve time of a second, warm run."""
     import torch
     from paper_1908_08666_amd import Multigrid
     mgh = Multigrid(verts, level, coarse, **op)
@@ -114,14 +114,16 @@ def mg_solve(verts, level, op, k, b, coarse=2, rtol=1e-8, maxit=100):
             t_setup = time.perf_counter() - t0
             x = torch.zeros_like(b)
             t0 = time.perf_counter()
-            x, info = mgh.solve(b, x=x, rtol=rtol, maxit=maxit, raise_on_status=False)
+            x, info = mgh.solve(b, x=x, rtol=rtol, maxit=maxit, precision=precision,
+                                raise_on_status=False)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
     finally:
         mgh.close()
     return dict(iterations=info["iterations"], seconds=round(wall, 4),
                 setup_seconds=round(t_setup, 4), rel_residual=info["rel_residual"],
-                status=info["status"], levels=[coarse, level], cycle="V(3,3)", omega=0.7)
+                status=info["status"], levels=[coarse, level], cycle="V(3,3)", omega=0.7,
+                cycle_precision=precision)
 
 
 def carreau_workload(level, dev, solve=True, maxit=60000):
@@ -174,6 +176,7 @@ def carreau_workload(level, dev, solve=True, maxit=60000):
         ws = None
         torch.cuda.empty_cache()
         out["mg_pcg64"] = mg_solve(W.cube24(), level, dict(mu1=1.0), k, b)
+        out["mg_pcg64_f32cycle"] = mg_solve(W.cube24(), level, dict(mu1=1.0), k, b, precision="f32")
     return out
 
 
@@ -480,6 +483,8 @@ def main():
         ws = None
         torch.cuda.empty_cache()
         solves["mg_pcg64"] = mg_solve(W.kuhn6(), args.level, dict(mu1=mu, lam1=lam), k64, b)
+        solves["mg_pcg64_f32cycle"] = mg_solve(W.kuhn6(), args.level, dict(mu1=mu, lam1=lam), k64, b,
+                                               precision="f32")
         extra["solve_to_1e-8"] = solves
 
     if args.batch:

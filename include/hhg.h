@@ -424,7 +424,7 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  * convergence).  Errors: HHG_EINVAL (null or misaligned pointer, level out of
  * range, mixed levels, non-conforming mesh, a workspace without coefficient
  * setup, coarse level with more than 512 unknown nodes, nu1 + nu2 < 1,
- * omega outside (0, 2), unknown method), HHG_EHIP,
+ * omega outside (0, 2), unknown method or precision), HHG_EHIP,
  * HHG_EBREAKDOWN (singular coarse operator, or a breakdown of the solve),
  * HHG_ENOCONV (maxit reached; x and info are written).                     */
 typedef struct hhg_mg_s *hhg_mg;
@@ -435,6 +435,12 @@ typedef struct {
   double rtol;           /* hhg_mg_solve: ||b - A x|| <= rtol ||b||           */
   int32_t maxit;         /* hhg_mg_solve: iterations (CG steps or cycles)     */
   int32_t method;        /* hhg_mg_solve: hhg_mg_method                       */
+  int32_t precision;     /* arithmetic of the cycle, hhg_prec: HHG_F64, or
+                          * HHG_F32 (operator, smoother, transfers and vectors
+                          * of every level in FP32, coarse inverse FP64; r is
+                          * rounded to FP32 on entry and z widened on exit,
+                          * while the solve's residuals, dot products and
+                          * updates stay FP64)                                */
 } hhg_mg_opts;
 int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coarse_level,
                   hhg_mg *out);

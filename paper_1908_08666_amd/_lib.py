@@ -56,7 +56,8 @@ HHG_SAMPLE_BYTES = 128
 
 class MgOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
-                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 HHG_MG_CG, HHG_MG_CYCLE = 0, 1

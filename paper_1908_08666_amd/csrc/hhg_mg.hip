@@ -60,11 +60,11 @@ __device__ __forceinline__ int64_t local_slot(int n, int i, int j, int k) {
 // other fine node is the midpoint of the coarse lattice edge (F - d)/2 --
 // (F + d)/2, d the lattice direction with F's parity pattern.  Dirichlet
 // slots stay zero.  Grid: (positions, macro).
-template <bool ADD>
+template <bool ADD, typename T>
 __global__ __launch_bounds__(256) void k_prolong(const MacroInfo *__restrict__ mc,
                                                  const MacroInfo *__restrict__ mf,
                                                  const uint8_t *__restrict__ flf,
-                                                 const double *__restrict__ xc, double *__restrict__ xf,
+                                                 const T *__restrict__ xc, T *__restrict__ xf,
                                                  int64_t Nc, int64_t Nf) {
   const int m = blockIdx.y;
   const int nf = mf[m].n, nc = mc[m].n;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_prolong(const MacroInfo *__restrict__ m
   const int64_t sf = mf[m].off + q;
   int I, J, K;
   local_ijk(q, nf, I, J, K);
-  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  T v0 = T(0), v1 = T(0), v2 = T(0);
   if (!(flf[sf] & 1)) {
     const int pi = I & 1, pj = J & 1, pk = K & 1;
     const int64_t oc = mc[m].off;
@@ -90,9 +90,9 @@ __global__ __launch_bounds__(256) void k_prolong(const MacroInfo *__restrict__ m
       const int dk = pk ? ((pi ^ pj) ? -1 : 1) : 0;
       const int64_t sa = oc + local_slot(nc, (I - di) >> 1, (J - dj) >> 1, (K - dk) >> 1);
       const int64_t sb = oc + local_slot(nc, (I + di) >> 1, (J + dj) >> 1, (K + dk) >> 1);
-      v0 = 0.5 * (xc[sa] + xc[sb]);
-      v1 = 0.5 * (xc[Nc + sa] + xc[Nc + sb]);
-      v2 = 0.5 * (xc[2 * Nc + sa] + xc[2 * Nc + sb]);
+      v0 = T(0.5) * (xc[sa] + xc[sb]);
+      v1 = T(0.5) * (xc[Nc + sa] + xc[Nc + sb]);
+      v2 = T(0.5) * (xc[2 * Nc + sa] + xc[2 * Nc + sb]);
     }
   }
   if (ADD) {
@@ -111,25 +111,26 @@ __global__ __launch_bounds__(256) void k_prolong(const MacroInfo *__restrict__ m
 // each divided by the number of copies of the fine node, so that the sum over
 // the coarse copies (k_copy_sum3) counts every fine node once.  Dirichlet
 // coarse slots get zero.
+template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const MacroInfo *__restrict__ mc,
                                                   const MacroInfo *__restrict__ mf,
                                                   const uint8_t *__restrict__ flc,
                                                   const double *__restrict__ winv,
-                                                  const double *__restrict__ rf, double *__restrict__ rc,
+                                                  const T *__restrict__ rf, T *__restrict__ rc,
                                                   int64_t Nc, int64_t Nf) {
   const int m = blockIdx.y;
   const int nf = mf[m].n, nc = mc[m].n;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= macro_nodes(nc)) return;
   const int64_t sc = mc[m].off + q;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  T s0 = T(0), s1 = T(0), s2 = T(0);
   if (!(flc[sc] & 1)) {
     int i, j, k;
     local_ijk(q, nc, i, j, k);
     const int64_t of = mf[m].off;
     {
       const int64_t s = of + local_slot(nf, 2 * i, 2 * j, 2 * k);
-      const double w = winv[s];
+      const T w = (T)winv[s];
       s0 = w * rf[s];
       s1 = w * rf[Nf + s];
       s2 = w * rf[2 * Nf + s];
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_restrict(const MacroInfo *__restrict__ 
       const int a = 2 * i + DIR_I[d], b = 2 * j + DIR_J[d], c = 2 * k + DIR_K[d];
       if (a < 0 || b < 0 || c < 0 || a + b + c > nf) continue;
       const int64_t s = of + local_slot(nf, a, b, c);
-      const double w = 0.5 * winv[s];
+      const T w = (T)(0.5 * winv[s]);
       s0 = fma(w, rf[s], s0);
       s1 = fma(w, rf[Nf + s], s1);
       s2 = fma(w, rf[2 * Nf + s], s2);
@@ -151,13 +152,14 @@ __global__ __launch_bounds__(256) void k_restrict(const MacroInfo *__restrict__ 
 }
 
 // Sum over the copies of every interface group, written to all copies.
+template <typename T>
 __global__ __launch_bounds__(256) void k_copy_sum3(const int64_t *__restrict__ ptr,
                                                    const int64_t *__restrict__ slots, int64_t ng,
-                                                   double *__restrict__ v, int64_t N) {
+                                                   T *__restrict__ v, int64_t N) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
        g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a = ptr[g], b = ptr[g + 1];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
     for (int64_t q = a; q < b; ++q) {
       const int64_t s = slots[q];
       s0 += v[s];
@@ -188,18 +190,17 @@ __global__ __launch_bounds__(256) void k_inject(const MacroInfo *__restrict__ mc
 
 // x = omega P r (FIRST) or x += omega P r, P the inverse diagonal blocks
 // (xx yy zz xy xz yz, zero at Dirichlet slots)
-template <bool FIRST>
-__global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ P,
-                                                const double *__restrict__ r, double *__restrict__ x,
-                                                double omega, int64_t N) {
+template <bool FIRST, typename T>
+__global__ __launch_bounds__(256) void k_jacobi(const T *__restrict__ P, const T *__restrict__ r,
+                                                T *__restrict__ x, T omega, int64_t N) {
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N;
        s += (int64_t)gridDim.x * blockDim.x) {
-    const double r0 = r[s], r1 = r[N + s], r2 = r[2 * N + s];
-    const double Pxx = P[s], Pyy = P[N + s], Pzz = P[2 * N + s];
-    const double Pxy = P[3 * N + s], Pxz = P[4 * N + s], Pyz = P[5 * N + s];
-    const double z0 = omega * (Pxx * r0 + Pxy * r1 + Pxz * r2);
-    const double z1 = omega * (Pxy * r0 + Pyy * r1 + Pyz * r2);
-    const double z2 = omega * (Pxz * r0 + Pyz * r1 + Pzz * r2);
+    const T r0 = r[s], r1 = r[N + s], r2 = r[2 * N + s];
+    const T Pxx = P[s], Pyy = P[N + s], Pzz = P[2 * N + s];
+    const T Pxy = P[3 * N + s], Pxz = P[4 * N + s], Pyz = P[5 * N + s];
+    const T z0 = omega * (Pxx * r0 + Pxy * r1 + Pxz * r2);
+    const T z1 = omega * (Pxy * r0 + Pyy * r1 + Pyz * r2);
+    const T z2 = omega * (Pxz * r0 + Pyz * r1 + Pzz * r2);
     if (FIRST) {
       x[s] = z0;
       x[N + s] = z1;
@@ -212,10 +213,19 @@ __global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ P,
   }
 }
 
-__global__ void k_fill0(double *__restrict__ a, int64_t n) {
+template <typename T>
+__global__ void k_fill0(T *__restrict__ a, int64_t n) {
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x)
-    a[s] = 0.0;
+    a[s] = T(0);
+}
+
+// b = a converted to the other precision
+template <typename A, typename B>
+__global__ void k_cast(const A *__restrict__ a, B *__restrict__ b, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    b[s] = (B)a[s];
 }
 
 // unit vector of unknown coarse DoF (u, c) at every copy of node u
@@ -234,18 +244,20 @@ __global__ void k_column(const int64_t *__restrict__ owner, int nu, const double
 
 // x = A^{-1} b on the coarsest level: gather b at the owners, dense product
 // with the inverse (column-major, symmetric), scatter to every copy
+template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_solve(const int64_t *__restrict__ owner,
                                                       const int64_t *__restrict__ ptr,
                                                       const int64_t *__restrict__ slots, int nu,
                                                       const double *__restrict__ Ainv,
-                                                      const double *__restrict__ b,
-                                                      double *__restrict__ x, int64_t N) {
+                                                      const T *__restrict__ b,
+                                                      T *__restrict__ x, int64_t N) {
   const int n3 = 3 * nu;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n3; r += gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int c = 0; c < n3; ++c) s = fma(Ainv[(int64_t)c * n3 + r], b[(c % 3) * N + owner[c / 3]], s);
+    for (int c = 0; c < n3; ++c)
+      s = fma(Ainv[(int64_t)c * n3 + r], (double)b[(c % 3) * N + owner[c / 3]], s);
     const int u = r / 3, comp = r % 3;
-    for (int64_t q = ptr[u]; q < ptr[u + 1]; ++q) x[comp * N + slots[q]] = s;
+    for (int64_t q = ptr[u]; q < ptr[u + 1]; ++q) x[comp * N + slots[q]] = (T)s;
   }
 }
 
@@ -284,10 +296,32 @@ __global__ void k_xpby(double *__restrict__ p, const double *__restrict__ z, dou
 // ----------------------------------------------------------- workspace
 struct MgWork {
   std::vector<double *> k, P, b, x, r;   // per level
+  std::vector<float *> k32, P32, b32, x32, r32;   // per level, for FP32 cycles
   double *Ainv = nullptr;                // (3 n_cu)^2, inverse of the coarsest operator
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;   // CG vectors (finest)
   double *part = nullptr;                // MG_RED partial sums
 };
+
+// the per-level arrays of one precision
+template <typename T>
+struct LevelArrays {
+  const T *k, *P;
+  T *b, *x, *r;
+};
+template <typename T>
+LevelArrays<T> level_arrays(const MgWork &W, int q);
+template <>
+LevelArrays<double> level_arrays<double>(const MgWork &W, int q) {
+  return {W.k[q], W.P[q], W.b[q], W.x[q], W.r[q]};
+}
+template <>
+LevelArrays<float> level_arrays<float>(const MgWork &W, int q) {
+  return {W.k32[q], W.P32[q], W.b32[q], W.x32[q], W.r32[q]};
+}
+template <typename T>
+constexpr int prec_of() {
+  return sizeof(T) == 8 ? HHG_F64 : HHG_F32;
+}
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -295,6 +329,11 @@ size_t layout(const hhg_mg_s *mg, char *base, MgWork *w) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+    off += al256(bytes);
+    return p;
+  };
+  auto take32 = [&](size_t bytes) {
+    float *p = base ? reinterpret_cast<float *>(base + off) : nullptr;
     off += al256(bytes);
     return p;
   };
@@ -306,6 +345,11 @@ size_t layout(const hhg_mg_s *mg, char *base, MgWork *w) {
   W.b.assign(L, nullptr);
   W.x.assign(L, nullptr);
   W.r.assign(L, nullptr);
+  W.k32.assign(L, nullptr);
+  W.P32.assign(L, nullptr);
+  W.b32.assign(L, nullptr);
+  W.x32.assign(L, nullptr);
+  W.r32.assign(L, nullptr);
   for (int q = 0; q < L; ++q) {
     const size_t N = (size_t)mg->lev[q]->n_nodes;
     W.k[q] = take(8 * N);
@@ -313,6 +357,11 @@ size_t layout(const hhg_mg_s *mg, char *base, MgWork *w) {
     W.b[q] = take(24 * N);
     W.x[q] = take(24 * N);
     W.r[q] = take(24 * N);
+    W.k32[q] = take32(4 * N);
+    W.P32[q] = take32(24 * N);
+    W.b32[q] = take32(12 * N);
+    W.x32[q] = take32(12 * N);
+    W.r32[q] = take32(12 * N);
   }
   const size_t n3 = 3 * (size_t)mg->n_cu;
   W.Ainv = take(8 * n3 * n3);
@@ -372,66 +421,88 @@ dim3 macro_grid(const hhg_ctx *h) {
   return dim3((unsigned)((maxn + 255) / 256), (unsigned)h->n_macro);
 }
 
-int prolong(hhg_mg_s *mg, int q, const double *xc, double *xf, bool add, hipStream_t st) {
+template <typename T>
+int prolong(hhg_mg_s *mg, int q, const T *xc, T *xf, bool add, hipStream_t st) {
   hhg_ctx *c = mg->lev[q - 1], *f = mg->lev[q];
   if (add)
-    hipLaunchKernelGGL(k_prolong<true>, macro_grid(f), dim3(256), 0, st, c->d_minfo, f->d_minfo,
+    hipLaunchKernelGGL((k_prolong<true, T>), macro_grid(f), dim3(256), 0, st, c->d_minfo, f->d_minfo,
                        f->d_flags, xc, xf, c->n_nodes, f->n_nodes);
   else
-    hipLaunchKernelGGL(k_prolong<false>, macro_grid(f), dim3(256), 0, st, c->d_minfo, f->d_minfo,
+    hipLaunchKernelGGL((k_prolong<false, T>), macro_grid(f), dim3(256), 0, st, c->d_minfo, f->d_minfo,
                        f->d_flags, xc, xf, c->n_nodes, f->n_nodes);
   HHG_HIP(hipGetLastError());
   return HHG_OK;
 }
 
-int restrict_(hhg_mg_s *mg, int q, const double *rf, double *rc, hipStream_t st) {
+template <typename T>
+int restrict_(hhg_mg_s *mg, int q, const T *rf, T *rc, hipStream_t st) {
   hhg_ctx *c = mg->lev[q - 1], *f = mg->lev[q];
-  hipLaunchKernelGGL(k_restrict, macro_grid(c), dim3(256), 0, st, c->d_minfo, f->d_minfo, c->d_flags,
+  hipLaunchKernelGGL(k_restrict<T>, macro_grid(c), dim3(256), 0, st, c->d_minfo, f->d_minfo, c->d_flags,
                      mg->d_winv[q], rf, rc, c->n_nodes, f->n_nodes);
   HHG_HIP(hipGetLastError());
   if (c->n_grp > 0) {
-    hipLaunchKernelGGL(k_copy_sum3, grid1(c->n_grp), dim3(256), 0, st, c->d_grp_ptr, c->d_grp_slot,
-                       c->n_grp, rc, c->n_nodes);
+    hipLaunchKernelGGL(k_copy_sum3<T>, grid1(c->n_grp), dim3(256), 0, st, c->d_grp_ptr,
+                       c->d_grp_slot, c->n_grp, rc, c->n_nodes);
     HHG_HIP(hipGetLastError());
   }
   return HHG_OK;
 }
 
-// x_q = V-cycle applied to b_q (levels q and below)
-int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const double *b, double *x,
+// x_q = V-cycle applied to b_q (levels q and below), in the precision T
+// (operator, smoother and transfers in T; the coarse inverse is FP64)
+template <typename T>
+int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const T *b, T *x,
            hipStream_t st) {
   hhg_ctx *h = mg->lev[q];
   const int64_t N = h->n_nodes;
   if (q == 0) {
-    hipLaunchKernelGGL(k_fill0, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
+    hipLaunchKernelGGL(k_fill0<T>, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
     if (mg->n_cu > 0)
-      hipLaunchKernelGGL(k_coarse_solve, grid1(3 * mg->n_cu), dim3(256), 0, st, mg->d_cu_owner,
+      hipLaunchKernelGGL(k_coarse_solve<T>, grid1(3 * mg->n_cu), dim3(256), 0, st, mg->d_cu_owner,
                          mg->d_cu_ptr, mg->d_cu_slot, mg->n_cu, W.Ainv, b, x, N);
     HHG_HIP(hipGetLastError());
     return HHG_OK;
   }
   int rc;
-  double *r = W.r[q];
+  const LevelArrays<T> A = level_arrays<T>(W, q), C = level_arrays<T>(W, q - 1);
+  T *r = A.r;
+  const T omega = (T)o.omega;
   auto smooth = [&](bool first) -> int {
     if (first) {
-      hipLaunchKernelGGL(k_jacobi<true>, grid1(N), dim3(256), 0, st, W.P[q], b, x, o.omega, N);
+      hipLaunchKernelGGL((k_jacobi<true, T>), grid1(N), dim3(256), 0, st, A.P, b, x, omega, N);
     } else {
-      const int rc2 = apply_internal(h, HHG_F64, mg->method, b, x, W.k[q], r, st);
+      const int rc2 = apply_internal(h, prec_of<T>(), mg->method, b, x, A.k, r, st);
       if (rc2) return rc2;
-      hipLaunchKernelGGL(k_jacobi<false>, grid1(N), dim3(256), 0, st, W.P[q], r, x, o.omega, N);
+      hipLaunchKernelGGL((k_jacobi<false, T>), grid1(N), dim3(256), 0, st, A.P, r, x, omega, N);
     }
     HHG_HIP(hipGetLastError());
     return HHG_OK;
   };
   for (int s = 0; s < o.nu1; ++s)
     if ((rc = smooth(s == 0))) return rc;
-  if (o.nu1 == 0) hipLaunchKernelGGL(k_fill0, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
-  if ((rc = apply_internal(h, HHG_F64, mg->method, b, x, W.k[q], r, st))) return rc;
-  if ((rc = restrict_(mg, q, r, W.b[q - 1], st))) return rc;
-  if ((rc = vcycle(mg, W, o, q - 1, W.b[q - 1], W.x[q - 1], st))) return rc;
-  if ((rc = prolong(mg, q, W.x[q - 1], x, true, st))) return rc;
+  if (o.nu1 == 0) hipLaunchKernelGGL(k_fill0<T>, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
+  if ((rc = apply_internal(h, prec_of<T>(), mg->method, b, x, A.k, r, st))) return rc;
+  if ((rc = restrict_<T>(mg, q, r, C.b, st))) return rc;
+  if ((rc = vcycle<T>(mg, W, o, q - 1, C.b, C.x, st))) return rc;
+  if ((rc = prolong<T>(mg, q, C.x, x, true, st))) return rc;
   for (int s = 0; s < o.nu2; ++s)
     if ((rc = smooth(false))) return rc;
+  return HHG_OK;
+}
+
+// z = V(r) on the finest level in the precision the options select: an FP32
+// cycle runs on FP32 copies of r and z
+int finest_cycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, const double *r, double *z,
+                 hipStream_t st) {
+  const int F = (int)mg->lev.size() - 1;
+  if (o.precision == HHG_F64) return vcycle<double>(mg, W, o, F, r, z, st);
+  const int64_t n3 = 3 * mg->lev[F]->n_nodes;
+  hipLaunchKernelGGL((k_cast<double, float>), grid1(n3), dim3(256), 0, st, r, W.b32[F], n3);
+  HHG_HIP(hipGetLastError());
+  const int rc = vcycle<float>(mg, W, o, F, W.b32[F], W.x32[F], st);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_cast<float, double>), grid1(n3), dim3(256), 0, st, W.x32[F], z, n3);
+  HHG_HIP(hipGetLastError());
   return HHG_OK;
 }
 
@@ -501,6 +572,8 @@ int check_opts(const hhg_mg_opts *o) {
   if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(HHG_EINVAL, "omega must lie in (0, 2)");
   if (o->method != HHG_MG_CG && o->method != HHG_MG_CYCLE)
     return fail(HHG_EINVAL, "unknown multigrid solve method");
+  if (o->precision != HHG_F64 && o->precision != HHG_F32)
+    return fail(HHG_EINVAL, "cycle precision must be HHG_F64 or HHG_F32");
   return HHG_OK;
 }
 
@@ -596,7 +669,7 @@ int hhg_mg_prolong(hhg_mg mg, int32_t fine_level, const double *xc, double *xf, 
   if (fine_level <= mg->coarse_level || fine_level > mg->fine_level)
     return fail(HHG_EINVAL, "fine level out of range");
   if ((rc = mg_device(mg))) return rc;
-  return prolong(mg, fine_level - mg->coarse_level, xc, xf, false, (hipStream_t)stream);
+  return prolong<double>(mg, fine_level - mg->coarse_level, xc, xf, false, (hipStream_t)stream);
 }
 
 int hhg_mg_restrict(hhg_mg mg, int32_t fine_level, const double *rf, double *rc_, void *stream) {
@@ -606,7 +679,7 @@ int hhg_mg_restrict(hhg_mg mg, int32_t fine_level, const double *rf, double *rc_
   if (fine_level <= mg->coarse_level || fine_level > mg->fine_level)
     return fail(HHG_EINVAL, "fine level out of range");
   if ((rc = mg_device(mg))) return rc;
-  return restrict_(mg, fine_level - mg->coarse_level, rf, rc_, (hipStream_t)stream);
+  return restrict_<double>(mg, fine_level - mg->coarse_level, rf, rc_, (hipStream_t)stream);
 }
 
 int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *workspace,
@@ -631,16 +704,23 @@ int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *w
                        W.k[q - 1]);
     HHG_HIP(hipGetLastError());
   }
-  for (int q = 0; q < L; ++q)
+  for (int q = 0; q < L; ++q) {
     if ((rc = hhg_preconditioner(mg->lev[q], HHG_PRECOND_BLOCK_JACOBI, method, W.k[q], W.P[q],
                                  st)))
       return rc;
+    // FP32 copies for FP32 cycles
+    const int64_t N = mg->lev[q]->n_nodes;
+    hipLaunchKernelGGL((k_cast<double, float>), grid1(N), dim3(256), 0, st, W.k[q], W.k32[q], N);
+    hipLaunchKernelGGL((k_cast<double, float>), grid1(6 * N), dim3(256), 0, st, W.P[q], W.P32[q],
+                       6 * N);
+    HHG_HIP(hipGetLastError());
+  }
   // dense coarsest operator, column by column, then its inverse on the host
   hhg_ctx *c = mg->lev[0];
   const int n3 = 3 * mg->n_cu;
   const int64_t N0 = c->n_nodes;
   for (int col = 0; col < n3; ++col) {
-    hipLaunchKernelGGL(k_fill0, grid1(3 * N0), dim3(256), 0, st, W.b[0], 3 * N0);
+    hipLaunchKernelGGL(k_fill0<double>, grid1(3 * N0), dim3(256), 0, st, W.b[0], 3 * N0);
     hipLaunchKernelGGL(k_unit, dim3(1), dim3(64), 0, st, mg->d_cu_ptr, mg->d_cu_slot, col / 3, col % 3,
                        W.b[0], N0);
     HHG_HIP(hipGetLastError());
@@ -677,7 +757,7 @@ int hhg_mg_vcycle(hhg_mg mg, const hhg_mg_opts *o, const double *r, double *z, v
   if ((rc = mg_device(mg))) return rc;
   MgWork W;
   layout(mg, static_cast<char *>(workspace), &W);
-  return vcycle(mg, W, *o, (int)mg->lev.size() - 1, r, z, (hipStream_t)stream);
+  return finest_cycle(mg, W, *o, r, z, (hipStream_t)stream);
 }
 
 int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, void *workspace,
@@ -711,7 +791,7 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
   if (use_graph) {
     hipGraph_t graph = nullptr;
     HHG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    const int crc = vcycle(mg, W, *o, F, W.pr, W.pz, st);
+    const int crc = finest_cycle(mg, W, *o, W.pr, W.pz, st);
     const hipError_t ce = hipStreamEndCapture(st, &graph);
     if (crc) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -733,7 +813,7 @@ int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, vo
       HHG_HIP(hipGraphLaunch(exec, st));
       return HHG_OK;
     }
-    return vcycle(mg, W, *o, F, W.pr, W.pz, st);
+    return finest_cycle(mg, W, *o, W.pr, W.pz, st);
   };
   double bb = 0.0, rr = 0.0, rho = 0.0, pq = 0.0;
   if ((rc = dot(mg, W, b, b, &bb, st))) return rc;

@@ -326,9 +326,10 @@ class Multigrid:
         return ctypes.c_void_p(base + ((-base) % 256))
 
     @staticmethod
-    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100, method="cg"):
+    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100, method="cg", precision="f64"):
         m = {"cg": L.HHG_MG_CG, "cycle": L.HHG_MG_CYCLE}[method]
-        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), m)
+        p = {"f64": L.HHG_F64, "f32": L.HHG_F32}[precision]
+        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), m, p)
 
     def prolong(self, fine_level, xc, xf=None, stream=None):
         """xf = P xc (``hhg_mg_prolong``)."""
@@ -365,28 +366,30 @@ class Multigrid:
         L.check(self._lib.hhg_mg_setup_coefficient(self._mg, m, _dev_ptr(k, (f.n_nodes,), torch.float64),
                                                     ws, _stream_ptr(stream)))
 
-    def vcycle(self, r, z=None, nu1=3, nu2=3, omega=0.7, stream=None):
-        """z = V(r) on the finest level (``hhg_mg_vcycle``)."""
+    def vcycle(self, r, z=None, nu1=3, nu2=3, omega=0.7, precision="f64", stream=None):
+        """z = V(r) on the finest level (``hhg_mg_vcycle``); precision "f32"
+        runs the cycle in FP32 on rounded copies of r and z."""
         import torch
         f = self.meshes[-1]
         if z is None:
             z = torch.empty_like(r)
-        o = self._opts(nu1, nu2, omega)
+        o = self._opts(nu1, nu2, omega, precision=precision)
         L.check(self._lib.hhg_mg_vcycle(self._mg, ctypes.byref(o), _dev_ptr(r, (3, f.n_nodes), torch.float64),
                                         _dev_ptr(z, (3, f.n_nodes), torch.float64),
                                         self._workspace(r.device), _stream_ptr(stream)))
         return z
 
     def solve(self, b, x=None, nu1=3, nu2=3, omega=0.7, rtol=1e-8, maxit=100, method="cg",
-              stream=None, raise_on_status=True):
+              precision="f64", stream=None, raise_on_status=True):
         """A x = b by V-cycle-preconditioned CG (method "cg") or the V-cycle
         iteration (method "cycle") (``hhg_mg_solve``); call setup_coefficient
-        first.  Returns (x, info dict)."""
+        first.  precision "f32" runs the V-cycles in FP32 (the outer
+        iteration stays FP64).  Returns (x, info dict)."""
         import torch
         f = self.meshes[-1]
         if x is None:
             x = torch.zeros((3, f.n_nodes), dtype=torch.float64, device=b.device)
-        o = self._opts(nu1, nu2, omega, rtol, maxit, method)
+        o = self._opts(nu1, nu2, omega, rtol, maxit, method, precision)
         info = L.SolveInfo()
         rc = self._lib.hhg_mg_solve(self._mg, ctypes.byref(o), _dev_ptr(b, (3, f.n_nodes), torch.float64),
                                     _dev_ptr(x, (3, f.n_nodes), torch.float64), self._workspace(b.device),

@@ -135,6 +135,14 @@ def test_invalid_arguments_rejected():
         mg.vcycle(r, nu1=0, nu2=0)
     with pytest.raises(HHGError):
         mg.vcycle(r, omega=2.5)
+    import ctypes
+    from paper_1908_08666_amd import _lib as L
+    o = L.MgOpts(3, 3, 0.7, 1e-8, 10, L.HHG_MG_CG, 7)      # unknown cycle precision
+    z = torch.empty_like(r)
+    ws = mg._workspace(r.device)
+    assert mg._lib.hhg_mg_vcycle(mg._mg, ctypes.byref(o), ctypes.c_void_p(r.data_ptr()),
+                                 ctypes.c_void_p(z.data_ptr()), ws, None) == L.HHG_EINVAL
+    assert b"precision" in mg._lib.hhg_last_error()
 
 
 def test_graph_replayed_cycles_match_eager_cycles(monkeypatch):
@@ -209,3 +217,48 @@ def test_vcycle_variants_match_oracle(method, iface, corr):
         xs = node_vec(spla.spsolve(H.A[-1].tocsc(), dof_vec(r, f)), f)
         assert rel_err(x[f.unknown], xs[f.unknown]) <= 1e-8
 
+
+
+def test_fp32_vcycle_matches_oracle():
+    """An FP32 cycle (operator, smoother, transfers in FP32, coarse inverse
+    FP64) against the oracle's FP64 cycle.  Bound: FP32 rounding (6e-8)
+    of each apply, amplified by the cancellation in the residuals and by the
+    smoothing steps of the levels (measured 1.1e-7 at this size); 2e-6
+    relative leaves room while a wrong term in any kernel, or an FP32 coarse
+    inverse, gives far more."""
+    mg, orcs, s2n, V = hierarchy("kuhn6", 4)
+    f = orcs[-1]
+    k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 0), 16, 1.0)
+    H = MG.Hierarchy(V, mg.coarse_level, 4, k, EFORM)
+    mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda())
+    r, r_d = consistent_random(f, s2n[-1], 31)
+    z = gather_consistent(mg.vcycle(r_d, precision="f32").cpu().numpy(), s2n[-1], f.n_nodes)
+    ref = node_vec(MG.vcycle(H, dof_vec(r, f)), f)
+    assert np.all(z[f.dirichlet] == 0)
+    err = rel_err(z[f.unknown], ref[f.unknown])
+    print(f"  FP32 V(3,3): rel err {err:.2e}", flush=True)
+    assert err <= 2e-6
+
+
+@pytest.mark.parametrize("method", ["cg", "cycle"])
+def test_fp32_cycles_reach_fp64_accuracy(method):
+    """With FP32 cycles the outer iteration keeps its FP64 residuals, so the
+    solve still reaches 1e-10 and the direct solution, in about as many
+    iterations as with FP64 cycles."""
+    mg, orcs, s2n, V = hierarchy("kuhn6", 4)
+    f = orcs[-1]
+    k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 0), 16, 1.0)
+    mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda())
+    b, b_d = consistent_random(f, s2n[-1], 44)
+    its = {}
+    for prec in ("f64", "f32"):
+        x_d, info = mg.solve(b_d, rtol=1e-10, maxit=80, method=method, precision=prec)
+        print(f"  {method} {prec}: {info['iterations']} iterations, rel residual "
+              f"{info['rel_residual']:.2e}", flush=True)
+        assert info["status"] == "HHG_OK" and info["rel_residual"] <= 1e-10
+        its[prec] = info["iterations"]
+    x = gather_consistent(x_d.cpu().numpy(), s2n[-1], f.n_nodes)
+    A = O.reduce_dirichlet(f, O.operator_matrix(f, k, EFORM)).tocsc()
+    xs = node_vec(spla.spsolve(A, dof_vec(b, f)), f)
+    assert rel_err(x[f.unknown], xs[f.unknown]) <= 1e-8
+    assert its["f32"] <= its["f64"] + 2, its
