@@ -211,13 +211,6 @@ __device__ __forceinline__ void interior_item(
       act[u] = col_ok[u] && sp + kk <= n - 1;
       yv[u][0] = yv[u][1] = yv[u][2] = T(0);
       if (act[u]) {
-        const int64_t g = gk + p;
-        T f0 = T(0), f1 = T(0), f2 = T(0);
-        if constexpr (RESID) {
-          f0 = f[g];
-          f1 = f[g + nn];
-          f2 = f[g + 2 * nn];
-        }
         const int e0 = p - ws;
         const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
         const int o0 = (kk % 3) * wl + e0;
@@ -240,11 +233,6 @@ __device__ __forceinline__ void interior_item(
         __builtin_amdgcn_sched_barrier(0);
         T y0, y1, y2;
         node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
-        if constexpr (RESID) {
-          y0 = f0 - y0;
-          y1 = f1 - y1;
-          y2 = f2 - y2;
-        }
         yv[u][0] = y0;
         yv[u][1] = y1;
         yv[u][2] = y2;
@@ -252,13 +240,21 @@ __device__ __forceinline__ void interior_item(
     }
     __syncthreads();
     if (more) put(kk + 2, pre);          // overwrites the slot of plane kk-1
+    // a residual reads f only now: loaded before the stencil, its three
+    // values would stay live across it and cost a wave of occupancy
 #pragma unroll
     for (int u = 0; u < NSUB; ++u)
       if (act[u]) {
         const int64_t g = gk + ps_[u];
-        y[g] = yv[u][0];
-        y[g + nn] = yv[u][1];
-        y[g + 2 * nn] = yv[u][2];
+        if constexpr (RESID) {
+          y[g] = f[g] - yv[u][0];
+          y[g + nn] = f[g + nn] - yv[u][1];
+          y[g + 2 * nn] = f[g + 2 * nn] - yv[u][2];
+        } else {
+          y[g] = yv[u][0];
+          y[g + nn] = yv[u][1];
+          y[g + 2 * nn] = yv[u][2];
+        }
       }
     __syncthreads();
   }

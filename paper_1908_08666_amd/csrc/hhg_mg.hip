@@ -242,8 +242,11 @@ __global__ void k_column(const int64_t *__restrict__ owner, int nu, const double
     A[(int64_t)col * n3 + r] = y[(r % 3) * N + owner[r / 3]];
 }
 
-// x = A^{-1} b on the coarsest level: gather b at the owners, dense product
-// with the inverse (column-major, symmetric), scatter to every copy
+constexpr int MG_MAX_CU = 512;           // unknown nodes of the coarsest level, at most
+
+// x = A^{-1} b on the coarsest level: gather b at the owners into LDS, dense
+// product with the inverse (column-major: entry (r, c) at c n3 + r), scatter
+// to every copy.  One thread per row; the grid covers the 3 nu rows once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_solve(const int64_t *__restrict__ owner,
                                                       const int64_t *__restrict__ ptr,
@@ -251,14 +254,19 @@ __global__ __launch_bounds__(256) void k_coarse_solve(const int64_t *__restrict_
                                                       const double *__restrict__ Ainv,
                                                       const T *__restrict__ b,
                                                       T *__restrict__ x, int64_t N) {
+  __shared__ double bl[3 * MG_MAX_CU];
   const int n3 = 3 * nu;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n3; r += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < n3; ++c)
-      s = fma(Ainv[(int64_t)c * n3 + r], (double)b[(c % 3) * N + owner[c / 3]], s);
-    const int u = r / 3, comp = r % 3;
-    for (int64_t q = ptr[u]; q < ptr[u + 1]; ++q) x[comp * N + slots[q]] = (T)s;
-  }
+  for (int c = threadIdx.x; c < n3; c += blockDim.x) bl[c] = (double)b[(c % 3) * N + owner[c / 3]];
+  __syncthreads();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n3) return;
+  double s = 0.0;
+  // the column loads are independent of the sum: unrolled, they are in
+  // flight together instead of one memory latency per column
+#pragma unroll 8
+  for (int c = 0; c < n3; ++c) s = fma(Ainv[(int64_t)c * n3 + r], bl[c], s);
+  const int u = r / 3, comp = r % 3;
+  for (int64_t q = ptr[u]; q < ptr[u + 1]; ++q) x[comp * N + slots[q]] = (T)s;
 }
 
 // partial sums of (a, b) over unknown owner slots
@@ -629,7 +637,7 @@ int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coar
     mg->cu_ptr.push_back((int64_t)mg->cu_slot.size());
   }
   mg->n_cu = (int)mg->cu_owner.size();
-  if (mg->n_cu > 512) {
+  if (mg->n_cu > MG_MAX_CU) {
     hhg_mg_destroy(mg);
     return fail(HHG_EINVAL, "coarse level too fine for the dense coarse solve (more than 512 unknown nodes)");
   }
