@@ -120,3 +120,39 @@ def test_null_arguments():
     assert lib.hhg_residual(None, 0, 0, None, None, None, None, None) == L.HHG_EINVAL
     assert lib.hhg_destroy(None) == L.HHG_OK
     assert b"null" in lib.hhg_last_error()
+
+
+_STRUCTS = {"hhg_mesh_desc": "MeshDesc", "hhg_op_desc": "OpDesc", "hhg_solve_opts": "SolveOpts",
+            "hhg_solve_info": "SolveInfo", "hhg_carreau": "Carreau", "hhg_tune_report": "TuneReport",
+            "hhg_train_opts": "TrainOpts", "hhg_mg_opts": "MgOpts"}
+
+
+def declared_structs():
+    """Field names, in order, of every typedef struct in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(hhg_\w+)\s*;", text, re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            # "int32_t nu1, nu2" / "const double *xyz" / "int64_t counts[6]"
+            first, *rest = [d.strip() for d in decl.split(",")]
+            names = [re.findall(r"(\w+)\s*(?:\[[^\]]*\])?$", first)[0]]
+            names += [re.findall(r"(\w+)\s*(?:\[[^\]]*\])?$", d.lstrip("*").strip())[0] for d in rest]
+            fields += names
+        out[name] = fields
+    return out
+
+
+def test_bindings_mirror_the_header_structs():
+    """Every option/descriptor struct of the header has a ctypes mirror with
+    the same fields in the same order (a missing or reordered field shifts
+    every later one)."""
+    from paper_1908_08666_amd import _lib as L
+    structs = declared_structs()
+    assert set(_STRUCTS) <= set(structs), sorted(structs)
+    for cname, pyname in _STRUCTS.items():
+        py = [f[0] for f in getattr(L, pyname)._fields_]
+        assert py == structs[cname], (cname, py, structs[cname])
