@@ -34,7 +34,7 @@ int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *
 
 namespace {
 
-constexpr int MG_RED = 512;              // blocks of the dot-product kernel
+constexpr int MG_RED = 2048;             // blocks of the dot-product kernel (8 per CU)
 
 dim3 grid1(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65535))); }
 

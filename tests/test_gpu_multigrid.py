@@ -219,24 +219,30 @@ def test_vcycle_variants_match_oracle(method, iface, corr):
 
 
 
-def test_fp32_vcycle_matches_oracle():
+@pytest.mark.parametrize("name,level,method,iface", [("kuhn6", 4, "scaled", "symmetric"),
+                                                      ("cube24", 3, "scaled", "symmetric"),
+                                                      ("kuhn6", 4, "onthefly", "symmetric"),
+                                                      ("kuhn6", 4, "scaled", "rowwise")])
+def test_fp32_vcycle_matches_oracle(name, level, method, iface):
     """An FP32 cycle (operator, smoother, transfers in FP32, coarse inverse
-    FP64) against the oracle's FP64 cycle.  Bound: FP32 rounding (6e-8)
-    of each apply, amplified by the cancellation in the residuals and by the
-    smoothing steps of the levels (measured 1.1e-7 at this size); 2e-6
-    relative leaves room while a wrong term in any kernel, or an FP32 coarse
-    inverse, gives far more."""
-    mg, orcs, s2n, V = hierarchy("kuhn6", 4)
+    FP64) against the oracle's FP64 cycle of the same operator.  Bound: FP32
+    rounding (6e-8) of each apply, amplified by the cancellation in the
+    residuals and by the smoothing steps of the levels (measured 1.1e-7 on
+    the Kuhn cube at level 4); 2e-6 relative leaves room while a wrong term
+    in any kernel, or an FP32 coarse inverse, gives far more."""
+    mg, orcs, s2n, V = hierarchy(name, level, iface=iface)
     f = orcs[-1]
     k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 0), 16, 1.0)
-    H = MG.Hierarchy(V, mg.coarse_level, 4, k, EFORM)
-    mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda())
+    H = MG.Hierarchy(V, mg.coarse_level, level, k, EFORM,
+                     method="nodal" if method == "onthefly" else "scaled",
+                     **({} if method == "onthefly" else dict(iface=iface)))
+    mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda(), method=method)
     r, r_d = consistent_random(f, s2n[-1], 31)
     z = gather_consistent(mg.vcycle(r_d, precision="f32").cpu().numpy(), s2n[-1], f.n_nodes)
     ref = node_vec(MG.vcycle(H, dof_vec(r, f)), f)
     assert np.all(z[f.dirichlet] == 0)
     err = rel_err(z[f.unknown], ref[f.unknown])
-    print(f"  FP32 V(3,3): rel err {err:.2e}", flush=True)
+    print(f"  {name} level {level} {method} {iface}: FP32 V(3,3) rel err {err:.2e}", flush=True)
     assert err <= 2e-6
 
 
