@@ -326,6 +326,8 @@ def main():
                     help="also train the learned block smoother and compare FCG solves (24 macros, level 6)")
     ap.add_argument("--elastostatics", action="store_true",
                     help="also run the paper's manufactured-solution benchmark (V-cycles, levels 3..7)")
+    ap.add_argument("--elastostatics-m", default="1,8",
+                    help="frequencies m of the modulus cos(m pi xyz) + 2 (the paper: 1,2,3,8)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB FP64 buffer 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -516,7 +518,9 @@ def main():
         extra["elastostatics_kuhn6"] = dict(
             levels=[3, 4, 5, 6, 7], finest=7, paper_levels=[1, 2, 3, 4, 5],
             load="consistent mass matrix times the interpolated body force",
-            results=ELS.benchmark([3, 4, 5, 6, 7], 7, ms=(1, 8), variants=variants, dev=dev))
+            results=ELS.benchmark([3, 4, 5, 6, 7], 7,
+                                  ms=tuple(int(m) for m in args.elastostatics_m.split(",")),
+                                  variants=variants, dev=dev))
 
     cpu = None
     if not args.no_cpu_baseline:
