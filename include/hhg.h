@@ -416,7 +416,8 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  * consistent, 16-byte aligned); Dirichlet entries are ignored on input and
  * written 0.  The caller owns every vector and the workspace
  * (hhg_mg_workspace_bytes, 256-byte aligned), which holds the per-level
- * coefficients, inverse blocks, vectors and the coarse inverse between
+ * coefficients, inverse blocks and vectors (FP64, and FP32 copies for FP32
+ * cycles) and the coarse inverse between
  * hhg_mg_setup_coefficient and the cycles that use them (cycles and solves
  * accept only the workspace of the last coefficient setup).  Calls are
  * asynchronous on the stream except hhg_mg_create, hhg_mg_setup_coefficient
