@@ -514,6 +514,8 @@ def main():
             "unphysical": dict(corr="none", op_method="scaled", iface="rowwise", method="cycle"),
             "physical_symmetric_rule": dict(corr="physical", op_method="scaled", iface="symmetric",
                                             method="cg"),
+            "physical_f32_cycles": dict(corr="physical", op_method="scaled", iface="rowwise",
+                                        method="cycle", precision="f32"),
         }
         extra["elastostatics_kuhn6"] = dict(
             levels=[3, 4, 5, 6, 7], finest=7, paper_levels=[1, 2, 3, 4, 5],

@@ -69,9 +69,10 @@ def consistent_load(xyz, F, level):
 
 
 def solve_level(level, m, corr="physical", iface="rowwise", method="cycle", op_method="scaled",
-                load="consistent", rtol=1e-8, maxit=200, coarse=2, dev="cuda"):
+                load="consistent", rtol=1e-8, maxit=200, coarse=2, precision="f64", dev="cuda"):
     """Discrete solution on one level: (u_h [3, n_slots] with the boundary
-    values, solve info, seconds of the solve)."""
+    values, solve info, seconds of the solve).  precision: arithmetic of the
+    V-cycles ("f64" or "f32"; residuals and updates stay FP64)."""
     import torch
     import workloads as W
     from .hhg import Mesh, Multigrid
@@ -94,7 +95,8 @@ def solve_level(level, m, corr="physical", iface="rowwise", method="cycle", op_m
         mg.setup_coefficient(k, method=op_method)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        w, info = mg.solve(b, rtol=rtol, maxit=maxit, method=method, raise_on_status=False)
+        w, info = mg.solve(b, rtol=rtol, maxit=maxit, method=method, precision=precision,
+                           raise_on_status=False)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         return w + g, info, secs

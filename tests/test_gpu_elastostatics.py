@@ -33,3 +33,19 @@ def test_physical_scaling_converges_at_second_order():
     # without the correction the error stalls at the scaling's inconsistency
     assert unph[2]["error"] >= 5.0 * phys[2]["error"]
     assert unph[2]["eoc"] <= 0.5
+
+
+def test_fp32_cycles_keep_the_discretisation_error():
+    """V-cycles in FP32 inside the FP64 V-cycle iteration reach the same
+    discrete solution: the errors against u* agree with those of FP64 cycles
+    to far below the discretisation error (the algebraic error at the
+    stopping tolerance 1e-8 is what separates them)."""
+    from paper_1908_08666_amd import elastostatics as E
+    variants = {"f64": dict(corr="physical", op_method="scaled"),
+                "f32": dict(corr="physical", op_method="scaled", precision="f32")}
+    res = E.benchmark([3, 4, 5], 6, ms=(8,), variants=variants)
+    for a, b in zip(res["m8_f64"], res["m8_f32"]):
+        print(f"  level {a['level']}: FP64 cycles {a['error']:.6e} ({a['iterations']} it), "
+              f"FP32 cycles {b['error']:.6e} ({b['iterations']} it)", flush=True)
+        assert b["status"] == "HHG_OK" and b["iterations"] <= a["iterations"] + 2
+        assert abs(b["error"] - a["error"]) <= 1e-4 * a["error"]
