@@ -30,7 +30,7 @@ struct hhg_ctx {
   std::vector<int64_t> grp_ptr, grp_slot;    // non-Dirichlet copy groups
   std::vector<int64_t> agrp_ptr, agrp_slot;  // all copy groups
   int wl_max = 0;                            // LDS window entries per plane
-  int planes_per_item = 4;                   // default slab depth (planes per work item)
+  int planes_per_item = 5;                   // default slab depth (planes per work item)
   int slab_by_level[hhg::MAX_LEVEL + 1] = {};  // tuned slab depth per level (0: default)
   int persist_blocks = 0;                    // 0: one workgroup per item; else resident grid size
   int chunk = 256;                           // positions per interior work item
