@@ -133,7 +133,7 @@ int autotune_impl(hhg_ctx *h, int prec, int method, const void *x, const void *k
     rep->rows[li] = rows;
     const int n = 1 << L;
     double best = 1e30;
-    int best_q = h->planes_per_item;
+    int best_q = default_slab(h, L);
     for (int q = 1; q <= std::max(1, 2 * (n - 3)); q *= 2) {
       int tmp[MAX_LEVEL + 1] = {};
       tmp[L] = q;

@@ -30,7 +30,7 @@ struct hhg_ctx {
   std::vector<int64_t> grp_ptr, grp_slot;    // non-Dirichlet copy groups
   std::vector<int64_t> agrp_ptr, agrp_slot;  // all copy groups
   int wl_max = 0;                            // LDS window entries per plane
-  int planes_per_item = 5;                   // default slab depth (planes per work item)
+  int planes_per_item = 0;                   // slab depth of every level (HHG_PLANES_PER_ITEM); 0: by level
   int slab_by_level[hhg::MAX_LEVEL + 1] = {};  // tuned slab depth per level (0: default)
   int persist_blocks = 0;                    // 0: one workgroup per item; else resident grid size
   int chunk = 256;                           // positions per interior work item
@@ -95,6 +95,13 @@ int ensure_device(hhg_ctx *h);
 void build_work(const hhg_ctx *h, const std::vector<int> &macros, const int *slab,
                 std::vector<WorkItem> &out, int &wl_max);
 void free_graphs(hhg_ctx *h);
+// Default slab depth (planes per interior work item) of a level: deep slabs
+// spread each item's start-up (three planes loaded before the first row) on
+// the large levels; shallow ones give the small levels more items.
+inline int default_slab(const hhg_ctx *h, int level) {
+  if (h->planes_per_item > 0) return h->planes_per_item;
+  return level >= 7 ? 5 : 3;
+}
 
 // Brackets one kernel launch with events when profiling is enabled.
 class ProfScope {

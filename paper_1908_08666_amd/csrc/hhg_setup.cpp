@@ -680,7 +680,7 @@ void build_work(const hhg_ctx *h, const std::vector<int> &macros, const int *sla
   for (int m : macros) {
     const int n = h->minfo[m].n;
     const int lev = h->minfo[m].level;
-    const int depth = std::max(1, (slab && slab[lev] > 0) ? slab[lev] : h->planes_per_item);
+    const int depth = std::max(1, (slab && slab[lev] > 0) ? slab[lev] : default_slab(h, lev));
     const int64_t npos = tri(n - 1);  // interior positions live below T(n-1)
     const int nchunk = (int)((npos + CH - 1) / CH);
     std::vector<int> kmax(nchunk);
