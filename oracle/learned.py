@@ -12,8 +12,8 @@ block-Jacobi one, written out from its definition:
   neighbours, Sec. 2.4, Fig. subtypes_and_stencil), in the direction order
   me mw mse mnw tc bc ts bn mn ms tw be tse bnw.  A neighbour that is a
   Dirichlet node contributes 0, one outside the macro repeats the node's own
-  value.  The 15 values are divided by their mean (summed left to right
-  in that order, then divided by 15); the 16th feature is level / 8.  Features are rounded FP64 -> FP32 -> BF16 (nearest even).
+  value.  The 15 values are divided by their mean; the 16th feature is
+  level / 8.  Features are rounded FP64 -> FP32 -> BF16 (nearest even).
 * Network: h = relu(W1^T f + b1) (64 units, h rounded to BF16), o = W2^T h
   + b2 (9 outputs), with BF16 weights W1 (16x64), W2 (64x9) and FP32 biases.
   M = o as a row-major 3x3 matrix.
@@ -38,6 +38,8 @@ a tiny mesh; BF16 rounding against hand-computed bit patterns).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -57,6 +59,13 @@ def bf16_round(x) -> np.ndarray:
     lsb = (u >> 16) & 1
     u = (u + 0x7FFF + lsb) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_ulp(x) -> np.ndarray:
+    """Spacing of BF16 numbers at |x| (0 at x = 0)."""
+    a = np.abs(np.asarray(x, dtype=np.float64))
+    safe = np.where(a > 0, a, 1.0)
+    return np.where(a > 0, 2.0 ** (np.floor(np.log2(safe)) - 7), 0.0)
 
 
 # ------------------------------------------------------------------ params
@@ -102,10 +111,8 @@ def macro_features(mesh, m: int, k: np.ndarray) -> np.ndarray:
             g = gid[key[tuple(nb[q])]]
             col[q] = 0.0 if mesh.dirichlet[g] else k[g]
         vals[:, 1 + d] = col
-    total = vals[:, 0].copy()
-    for q in range(1, 15):                      # left to right, node first
-        total += vals[:, q]
-    mean = total / 15.0
+    # the mean of the 15 patch values, from their correctly rounded sum
+    mean = np.array([math.fsum(row) for row in vals]) / 15.0
     F = np.empty((ijk.shape[0], N_IN))
     F[:, :15] = vals / mean[:, None]
     F[:, 15] = n.bit_length() - 1

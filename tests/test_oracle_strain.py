@@ -74,6 +74,57 @@ def test_carreau_law():
     assert np.all(ST.carreau(eps2, 2.0, 1e-3, 5.0, 0.0) == 2.0)
 
 
+def test_carreau_values_by_hand():
+    """Eq. carreau at points where 1 + kappa |eps|^2 is a perfect power, so the
+    value follows by hand: 16^(-1/4) = 1/2 and 81^(-1/4) = 1/3 with the
+    constants of this build (eta0 1, eta_inf 1e-3, kappa 1, r -1/4); and the
+    paper's dimensionless blood constants (Sec. 5.2.2: eta0 140.764, eta_inf
+    1, kappa 212.2, r -0.325) at 1 + kappa |eps|^2 = 2^(40/13), where the
+    power is 2^(-1) exactly."""
+    law = dict(eta0=1.0, eta_inf=1e-3, kappa=1.0, r=-0.25)
+    got = ST.carreau(np.array([0.0, 15.0, 80.0]), **law)
+    assert got[0] == 1.0
+    assert abs(got[1] - (1e-3 + 0.999 / 2)) <= 1e-15        # 0.5005
+    assert abs(got[2] - (1e-3 + 0.999 / 3)) <= 1e-15        # 0.334
+    paper = dict(eta0=140.764, eta_inf=1.0, kappa=212.2, r=-0.325)
+    eps2 = (2.0 ** (40.0 / 13.0) - 1.0) / 212.2             # (1 + kappa eps2)^r = 2^(-1)
+    assert abs(ST.carreau(eps2, **paper) - (1.0 + 139.764 / 2)) <= 1e-12   # 70.882
+    assert ST.carreau(0.0, **paper) == 140.764
+
+
+def test_strain_rate_scale_by_hand():
+    """Simple shear u = (g y, 0, 0) has eps = g/2 (e_x e_y^T + e_y e_x^T), so
+    eps : eps = g^2 / 2; uniaxial stretch u = (a x, 0, 0) has eps : eps = a^2."""
+    g, a = 3.0, 5.0
+    G = np.zeros((2, 3, 3))
+    G[0, 0, 1] = g
+    G[1, 0, 0] = a
+    np.testing.assert_array_equal(ST.strain_rate_squared(G), [g * g / 2, a * a])
+
+
+def test_viscosity_of_simple_shear_by_hand(mesh):
+    """Affine simple shear with shear rate sqrt(30): eps : eps = 15 at every
+    node (the fit is exact for affine fields), so the viscosity is 0.5005."""
+    g = np.sqrt(30.0)
+    u = np.column_stack([g * mesh.xyz[:, 1], np.zeros(mesh.n_nodes), np.zeros(mesh.n_nodes)])
+    mu = ST.nodal_viscosity(mesh, u, 1.0, 1e-3, 1.0, -0.25)
+    np.testing.assert_allclose(mu, 0.5005, rtol=0, atol=1e-13)
+
+
+def test_seeded_velocity_gradient_converges():
+    """The seeded velocity field of the Carreau workloads: interior
+    least-squares gradients approach its analytic gradient at second order."""
+    errs = []
+    for L in (5, 6):                      # wave numbers up to 3: h = 1/32, 1/64 resolve them
+        mesh = MacroMesh(W.unit_tet(), L)
+        u = W.velocity_field(mesh.xyz, W.rng_for(3, 0), 0.1)
+        gx = W.velocity_gradient(mesh.xyz, W.rng_for(3, 0), 0.1)
+        G = ST.nodal_gradients(mesh, u)
+        inner = ~mesh.interface
+        errs.append(np.abs(G[inner] - gx[inner]).max() / np.abs(gx[inner]).max())
+    assert errs[1] < 0.05 and errs[0] / errs[1] > 3.5, errs
+
+
 def test_strain_rate_of_rotation_is_zero():
     G = np.zeros((4, 3, 3))
     G[:, 0, 1], G[:, 1, 0] = 1.0, -1.0
