@@ -76,7 +76,7 @@ enum hhg_method { HHG_METHOD_SCALED = 0, HHG_METHOD_ONTHEFLY = 1 };
 /* Macro mesh (Sec. 2: macro triangulation T_H refined uniformly).
  *   verts     host, [n_macro][4][3] vertex coordinates; the vertex order fixes
  *             each macro's index space (see the layout above).
- *   level     host, [n_macro]; 2 <= level <= 9 (a macro needs an interior
+ *   level     host, [n_macro]; 2 <= level <= 8 (a macro needs an interior
  *             vertex, Sec. 2).  CONFORMING meshes need one common level.
  *   coupling  HHG_CONFORMING: macros sharing faces/edges/vertices (matched by
  *             coordinates) form one problem; HHG_INDEPENDENT: every macro is
@@ -117,7 +117,7 @@ typedef struct {
  * uploaded to the current HIP device by the first device call, and the handle
  * may then only be used on that device.  On success *out owns host and device
  * memory until hhg_destroy.  Errors: HHG_EINVAL for null pointers,
- * n_macro < 1, a level outside 2..9, mixed levels in a conforming mesh, a
+ * n_macro < 1, a level outside 2..8, mixed levels in a conforming mesh, a
  * degenerate macro (|det| < 1e-12 |edges|^3) or unknown enum values;
  * HHG_EHIP / HHG_ENOMEM on device failures.                                  */
 int hhg_setup_macro(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_handle *out);
@@ -193,10 +193,13 @@ typedef struct {
 } hhg_solve_opts;
 
 typedef struct {
-  int32_t iterations;        /* CG iterations (all inner iterations for IR)   */
+  int32_t iterations;        /* CG iterations until the recursive residual met
+                                the tolerance (summed over the inner solves
+                                for IR; all run if it never did)              */
   int32_t outer_iterations;  /* IR refinement steps (1 for CG_F64)            */
   int32_t status;            /* HHG_OK, HHG_ENOCONV or HHG_EBREAKDOWN         */
-  int32_t pad;
+  int32_t iterations_run;    /* CG iterations executed: whole blocks of
+                                check_every, so up to check_every - 1 more    */
   double rel_residual;       /* ||b - A x|| / ||b|| recomputed in FP64        */
   double seconds;            /* wall time of the solve                        */
 } hhg_solve_info;
@@ -253,8 +256,10 @@ int hhg_nodal_viscosity(hhg_handle h, const double *u, const hhg_carreau *law, d
  *
  * hhg_autotune: times the interior kernel of `method` in precision `prec` on
  * the caller's x and k (device, as for hhg_apply_scaled), `reps` launches per
- * candidate after one warm-up: per level, over slab depths 1, 2, 4, ... planes
- * per item on that level's macros alone; then over the whole list, over grids
+ * candidate after one warm-up: per level, over balanced segments (-1: every
+ * chunk's run of planes cut into segments of equal cost, about one per
+ * resident workgroup) and slab depths 1, 2, 4, ... planes per item on that
+ * level's macros alone; then over the whole list, over grids
  * of one workgroup per item or a persistent grid of 1..4 x (compute units)
  * resident workgroups striding the list.  The fastest choices are kept in
  * the handle for every later apply, residual and solve; results do not
@@ -267,7 +272,7 @@ typedef struct {
   int32_t n_levels;          /* distinct levels, ascending in level[]        */
   int32_t persist_blocks;    /* chosen grid: 0 = one workgroup per item      */
   int32_t level[8];
-  int32_t slab[8];           /* chosen planes per work item                  */
+  int32_t slab[8];           /* chosen planes per work item (-1: balanced)   */
   int32_t macros[8];         /* macros of the level                          */
   int64_t rows[8];           /* macro-interior rows of the level             */
   double ms[8];              /* interior launch over the level's macros alone */
@@ -281,13 +286,14 @@ int hhg_autotune(hhg_handle h, int32_t prec, int32_t method, const void *x, cons
 
 /* hhg_set_tuning: adopts a tuning record (as filled by hhg_autotune, or
  * written by the caller) without timing anything: slab[q] planes per work
- * item for macros of level[q] (q < n_levels; 0 or an absent level keeps the
- * default depth of 4), and the grid (persist_blocks 0: one workgroup per work
+ * item for macros of level[q] (-1: balanced segments; q < n_levels; 0 or an
+ * absent level keeps the default depth: 5 planes from level 7 up, 3 below),
+ * and the grid (persist_blocks 0: one workgroup per work
  * item; else a multiple of 8 up to 65536 resident workgroups striding the
  * list).  Other fields are ignored.  Waits for all queued device work, then
  * replaces the handle's work list; graphs from hhg_graph_create are dropped.
  * Results do not depend on the record.  Errors: HHG_EINVAL for a null record,
- * levels outside 2..9, slabs outside 0..1024 or an invalid grid; HHG_EHIP.  */
+ * levels outside 2..8, slabs outside -1..1024 or an invalid grid; HHG_EHIP. */
 int hhg_set_tuning(hhg_handle h, const hhg_tune_report *tuning);
 
 /* hhg_graph_create: runs one checked apply y = A x (prec, method as in
@@ -465,6 +471,83 @@ int hhg_mg_vcycle(hhg_mg mg, const hhg_mg_opts *o, const double *r, double *z, v
 /* x: start vector on input, solution on output (finest level) */
 int hhg_mg_solve(hhg_mg mg, const hhg_mg_opts *o, const double *b, double *x, void *workspace,
                  hhg_solve_info *info, void *stream);
+
+/* ------------------------------------------------ generalized Stokes
+ * The incompressible generalized Stokes system of Sec. 5.2 (eqn.
+ * generalizedstokes, stress 2 mu eps(u) - p I), equal-order P1 velocity and
+ * pressure with the stabilization c_l(p, q) = -h_l^2/12 (grad p, grad q):
+ *     [ A(mu)  B^T ] [u]   [f]
+ *     [ B      C   ] [p] = [g],
+ * A(mu) the velocity operator 2 (mu eps(u), eps(v)) of the handle (mu its
+ * nodal coefficient), B[q, (j, l)] = -int d_l phi_j psi_q the divergence,
+ * C = c_l.  Velocities are device FP64 [3][n_nodes], pressures device FP64
+ * [n_nodes] (every node, all copies equal), 16-byte aligned.
+ *
+ * hhg_stokes_rows: one term on the handle's mesh, op
+ *   HHG_STOKES_DIV   out[n]    = B in[3][n]   (Dirichlet velocities read as 0)
+ *   HHG_STOKES_GRAD  out[3][n] = B^T in[n]    (Dirichlet rows 0)
+ *   HHG_STOKES_STAB  out[n]    = C in[n], with mesh width hl (> 0)
+ *   HHG_STOKES_MASS  out[n]    = int psi_q (lumped pressure mass; in unused)
+ * Asynchronous on `stream`.  Errors: HHG_EINVAL, HHG_EHIP.                  */
+enum hhg_stokes_op { HHG_STOKES_DIV = 0, HHG_STOKES_GRAD = 1, HHG_STOKES_STAB = 2,
+                     HHG_STOKES_MASS = 3 };
+int hhg_stokes_rows(hhg_handle h, int32_t op, double hl, const double *in, double *out,
+                    void *stream);
+
+/* Inexact Uzawa on the finest level of a multigrid handle (Sec. 5.2.1
+ * names an inexact Uzawa method with V(3,3) cycles and pressure relaxation):
+ *     u <- u + V(f - A u - B^T p)          (V: one cycle of hhg_mg_vcycle)
+ *     p <- p + omega_p (B u + C p - g) / S,  S_q = mass_q / mu_q - C_qq
+ *     p <- p - (mass . p) / (mass . 1)     (zero mean: the constant pressure
+ *                                           lies in the kernel when every
+ *                                           boundary node is Dirichlet)
+ * until ||[f - A u - B^T p; g - B u - C p]|| <= rtol ||[f; g]|| (2-norms over
+ * unknown velocity DoFs and all pressure nodes) or maxit steps.  The velocity
+ * multigrid must hold A(mu): call hhg_mg_setup_coefficient(mg, method, mu,
+ * mg_workspace) first.  u, p: start vectors on input, iterate on output.
+ * g may be null (zero).  stokes_workspace: hhg_mg_stokes_workspace_bytes,
+ * 256-byte aligned.  Synchronizes `stream` (every step reduces on the host).
+ * info: iterations, rel_residual, status (HHG_OK / HHG_ENOCONV).            */
+typedef struct {
+  int32_t nu1, nu2;      /* velocity V-cycle smoothing steps (paper: 3, 3)   */
+  double omega;          /* velocity block-Jacobi damping, e.g. 0.7          */
+  double omega_p;        /* pressure relaxation                              */
+  double h;              /* mesh width h_l of c_l; <= 0: 1 / 2^level (the
+                          * unit-cube meshes, one macro edge of length 1)    */
+  double rtol;           /* relative residual target                         */
+  int32_t maxit;         /* Uzawa steps                                      */
+  int32_t pad;
+} hhg_stokes_opts;
+int hhg_mg_stokes_workspace_bytes(hhg_mg mg, size_t *bytes);
+int hhg_mg_stokes_solve(hhg_mg mg, const hhg_stokes_opts *o, const double *f, const double *g,
+                        const double *mu, double *u, double *p, void *mg_workspace,
+                        void *stokes_workspace, hhg_solve_info *info, void *stream);
+
+/* Fixed-point (Picard) iteration for the Carreau fluid (Sec. 5.2.2, eq.
+ * fixpointsystem and Alg. fixedpoint_mg): from u = 0, p = 0 and
+ * mu = mu(u) (hhg_nodal_viscosity, Sec. 3), repeat: one inexact Uzawa step
+ * for the system with A(mu); mu = mu(u); until
+ * max_i |u_i - u_i(previous)| < 1e-3 max_i |u_i| (node-wise 2-norms over
+ * unknown nodes) or max_picard steps; then Uzawa steps with the last mu
+ * until the relative residual is <= o->rtol (the paper: 1e-3) or o->maxit,
+ * and a last mu = mu(u).  Uses the handle's operator (2 (mu eps, eps)) with
+ * method HHG_METHOD_SCALED or HHG_METHOD_ONTHEFLY.  f: [3][n]; u, p, mu:
+ * outputs.  Synchronizes `stream`.  info: picard steps, final Uzawa steps,
+ * final relative residual, status.                                          */
+typedef struct {
+  int32_t picard;            /* fixed-point steps                           */
+  int32_t final_iterations;  /* Uzawa steps of the final solve              */
+  int32_t status;            /* HHG_OK, or HHG_ENOCONV if either loop hit
+                                its limit                                    */
+  int32_t pad;
+  double rel_change;         /* last max |u - u_prev| / max |u|              */
+  double rel_residual;       /* of the final solve                          */
+  double seconds;
+} hhg_picard_info;
+int hhg_mg_stokes_picard(hhg_mg mg, const hhg_stokes_opts *o, const hhg_carreau *law,
+                         int32_t method, int32_t max_picard, const double *f, double *u,
+                         double *p, double *mu, void *mg_workspace, void *stokes_workspace,
+                         hhg_picard_info *info, void *stream);
 
 /* Kernel timing (tracing aid, not needed for results).  While enabled,
  * every kernel the library launches is bracketed by a pair of HIP events on

@@ -43,7 +43,7 @@ class SolveOpts(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("outer_iterations", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("iterations_run", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
@@ -79,6 +79,21 @@ class TuneReport(ctypes.Structure):
                 ("macros", ctypes.c_int32 * 8), ("rows", ctypes.c_int64 * 8),
                 ("ms", ctypes.c_double * 8), ("ms_total", ctypes.c_double),
                 ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+HHG_STOKES_DIV, HHG_STOKES_GRAD, HHG_STOKES_STAB, HHG_STOKES_MASS = 0, 1, 2, 3
+
+
+class StokesOpts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("omega_p", ctypes.c_double), ("h", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class PicardInfo(ctypes.Structure):
+    _fields_ = [("picard", ctypes.c_int32), ("final_iterations", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("rel_change", ctypes.c_double),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class HHGError(RuntimeError):
@@ -137,6 +152,12 @@ SIGNATURES = {
     "hhg_mg_vcycle": ([_VP, ctypes.POINTER(MgOpts), _VP, _VP, _VP, _VP], ctypes.c_int),
     "hhg_mg_solve": ([_VP, ctypes.POINTER(MgOpts), _VP, _VP, _VP, ctypes.POINTER(SolveInfo), _VP],
                      ctypes.c_int),
+    "hhg_stokes_rows": ([_VP, _I32, ctypes.c_double, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_mg_stokes_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hhg_mg_stokes_solve": ([_VP, ctypes.POINTER(StokesOpts), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                             ctypes.POINTER(SolveInfo), _VP], ctypes.c_int),
+    "hhg_mg_stokes_picard": ([_VP, ctypes.POINTER(StokesOpts), ctypes.POINTER(Carreau), _I32, _I32, _VP,
+                              _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(PicardInfo), _VP], ctypes.c_int),
     "hhg_profile_enable": ([_VP, _I32], ctypes.c_int),
     "hhg_profile_read": ([_VP, _I32, _I64P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hhg_last_error": ([], ctypes.c_char_p),

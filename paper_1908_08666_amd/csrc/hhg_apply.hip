@@ -114,18 +114,18 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
       for (int q = 0; q < np; ++q) ring += nk[RING_V[d][q]] + nk[RING_VM[d][q]];
       const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
       const T kh = fma(sc.w_end, ck + nk[d], wr * ring);
-      const T *S = sc.shat[d >> 1];
+      const T *S = sc.pr[d >> 1].shat;
       const T z0v = kh * nx0[d], z1v = kh * nx1[d], z2v = kh * nx2[d];
       sym_mv_acc(S, z0v, z1v, z2v, y0, y1, y2);
-      if constexpr (A0) sym_mv_acc(sc.a0[d >> 1], nx0[d], nx1[d], nx2[d], y0, y1, y2);
+      if constexpr (A0) sym_mv_acc(sc.pr[d >> 1].a0, nx0[d], nx1[d], nx2[d], y0, y1, y2);
       if (CORR) {
         T w0 = T(0), w1 = T(0), w2 = T(0);
 #pragma unroll
         for (int q = 0; q < np; ++q) {
           const T dk = nk[RING_V[d][q]] - nk[RING_VM[d][q]];
-          w0 = fma(dk, sc.cax[d][q][0], w0);
-          w1 = fma(dk, sc.cax[d][q][1], w1);
-          w2 = fma(dk, sc.cax[d][q][2], w2);
+          w0 = fma(dk, sc.pr[d >> 1].cax[q][0], w0);
+          w1 = fma(dk, sc.pr[d >> 1].cax[q][1], w1);
+          w2 = fma(dk, sc.pr[d >> 1].cax[q][2], w2);
         }
         cross_acc(w0, w1, w2, nx0[d], nx1[d], nx2[d], y0, y1, y2);
       }

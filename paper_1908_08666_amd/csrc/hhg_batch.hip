@@ -134,7 +134,8 @@ int autotune_impl(hhg_ctx *h, int prec, int method, const void *x, const void *k
     const int n = 1 << L;
     double best = 1e30;
     int best_q = default_slab(h, L);
-    for (int q = 1; q <= std::max(1, 2 * (n - 3)); q *= 2) {
+    // candidates: balanced segments, then slabs of 1, 2, 4, ... planes
+    for (int q = SLAB_BALANCED; q <= std::max(1, 2 * (n - 3)); q = q > 0 ? 2 * q : 1) {
       int tmp[MAX_LEVEL + 1] = {};
       tmp[L] = q;
       build_work(h, ms_of, tmp, items, wl);
@@ -235,8 +236,9 @@ int set_tuning(hhg_ctx *h, const hhg_tune_report *t) {
   int slab[MAX_LEVEL + 1] = {};
   for (int q = 0; q < t->n_levels; ++q) {
     const int L = t->level[q];
-    if (L < MIN_LEVEL || L > MAX_LEVEL) return fail(HHG_EINVAL, "level outside 2..9");
-    if (t->slab[q] < 0 || t->slab[q] > 1024) return fail(HHG_EINVAL, "slab outside 0..1024");
+    if (L < MIN_LEVEL || L > MAX_LEVEL) return fail(HHG_EINVAL, "level outside 2..8");
+    if (t->slab[q] < SLAB_BALANCED || t->slab[q] > 1024)
+      return fail(HHG_EINVAL, "slab outside -1..1024");
     slab[L] = t->slab[q];
   }
   int rc = ensure_device(h);

@@ -34,7 +34,6 @@ struct hhg_ctx {
   int slab_by_level[hhg::MAX_LEVEL + 1] = {};  // tuned slab depth per level (0: default)
   int persist_blocks = 0;                    // 0: one workgroup per item; else resident grid size
   int chunk = 256;                           // positions per interior work item
-  bool stage_dma = false;                    // interior staging by LDS-DMA loads (opt-in)
   bool serial_apply = false;                 // boundary rows on the caller's stream too
   bool on_device = false;                    // tables uploaded (first device call)
   int device = -1;
@@ -98,6 +97,11 @@ void free_graphs(hhg_ctx *h);
 // Default slab depth (planes per interior work item) of a level: deep slabs
 // spread each item's start-up (three planes loaded before the first row) on
 // the large levels; shallow ones give the small levels more items.
+// Slab depth (planes per interior work item) of a level: HHG_PLANES_PER_ITEM
+// when set, else 5 planes from level 7 up and 3 below.  SLAB_BALANCED asks
+// build_work for segments of equal cost instead (every chunk column cut
+// into about one segment per resident workgroup).
+constexpr int SLAB_BALANCED = -1;
 inline int default_slab(const hhg_ctx *h, int level) {
   if (h->planes_per_item > 0) return h->planes_per_item;
   return level >= 7 ? 5 : 3;

@@ -61,15 +61,18 @@ __device__ __forceinline__ void node_rows(const Node4<T> &c, const Node4<T> (&nb
 #pragma unroll
           for (int q = 0; q < np; ++q) {
             const T dk = nb[RING_V[d][q]].k - nb[RING_VM[d][q]].k;
-            w0 = fma(dk, sc.cax[d][q][0], w0);
-            w1 = fma(dk, sc.cax[d][q][1], w1);
-            w2 = fma(dk, sc.cax[d][q][2], w2);
+            w0 = fma(dk, sc.pr[pr].cax[q][0], w0);
+            w1 = fma(dk, sc.pr[pr].cax[q][1], w1);
+            w2 = fma(dk, sc.pr[pr].cax[q][2], w2);
           }
           cross_acc(w0, w1, w2, dx0, dx1, dx2, y0, y1, y2);
         }
       }
-      sym_mv_acc(sc.shat[pr], z0, z1, z2, y0, y1, y2);
-      if constexpr (A0) sym_mv_acc(sc.a0[pr], a0, a1, a2, y0, y1, y2);
+      sym_mv_acc(sc.pr[pr].shat, z0, z1, z2, y0, y1, y2);
+      if constexpr (A0) sym_mv_acc(sc.pr[pr].a0, a0, a1, a2, y0, y1, y2);
+      // one pair's constants at a time: loaded all at once they would not
+      // fit the scalar registers
+      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
 #pragma unroll
@@ -134,7 +137,9 @@ __device__ __forceinline__ void interior_item(
   const T *X2 = X1 + nn;
   const T *K = kc + mi.off;
 
-  // plane kk of the window: global -> registers (Dirichlet values of x zeroed)
+  // plane kk of the window: global -> registers.  Nothing here reads the
+  // loaded values, so the loads stay in flight until put() (a select on
+  // them at this point would make the wave wait for them at once).
   auto fetch = [&](int kk, Node4<T>(&dst)[NW]) {
     const int ps = (int)tri(n + 1 - kk);
     const int64_t base = plane_base(n, kk);
@@ -150,13 +155,11 @@ __device__ __forceinline__ void interior_item(
         v.x1 = X1[g];
         v.x2 = X2[g];
         v.k = K[g];
-        const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
-        if ((mi.dmask >> z) & 1u) v.x0 = v.x1 = v.x2 = T(0);
       }
       dst[r] = v;
     }
   };
-  // registers -> LDS slot of plane kk
+  // registers -> LDS slot of plane kk, Dirichlet values of x zeroed
   auto put = [&](int kk, const Node4<T>(&src)[NW]) {
     Pair<T> *da = bufA + (kk % 3) * wl;
     Pair<T> *db = bufB + (kk % 3) * wl;
@@ -164,8 +167,10 @@ __device__ __forceinline__ void interior_item(
     for (int r = 0; r < NW; ++r) {
       const int e = tid + r * TPB;
       if (e < wl) {
-        da[e] = Pair<T>{src[r].x0, src[r].x1};
-        db[e] = Pair<T>{src[r].x2, src[r].k};
+        const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
+        const bool dz = (mi.dmask >> z) & 1u;
+        da[e] = Pair<T>{dz ? T(0) : src[r].x0, dz ? T(0) : src[r].x1};
+        db[e] = Pair<T>{dz ? T(0) : src[r].x2, src[r].k};
       }
     }
   };
@@ -296,150 +301,6 @@ __global__ __launch_bounds__(TPB) void k_interior_persist(
 }
 
 
-// Same rows with the plane windows copied straight into LDS by the loader
-// (global_load_lds, 4 bytes per lane), so staging costs no registers and no
-// LDS write instructions.  Plane kk lives in slot kk % NSLOT as four arrays
-// (x0, x1, x2, k) of `wl` entries; plane kk+2 is loaded while plane kk is
-// computed, and one barrier per plane suffices: the slot being filled was
-// last read two planes earlier.  Every lane zeroes the Dirichlet values of x
-// among the entries it loaded itself, after its own loads have landed.
-constexpr int NSLOT = 4;
-
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int ROUNDS, int TPB>
-__global__ __launch_bounds__(TPB) void k_interior_dma(
-    const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
-    const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
-    const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *lds = reinterpret_cast<T *>(smem_raw);              // [NSLOT][4][wl]
-
-  const WorkItem w = work[blockIdx.x];
-  if (w.macro < 0) return;                  // padding item of the XCD-aware order
-  const MacroInfo mi = minfo[w.macro];
-  const int n = mi.n;
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int p0 = w.chunk * TPB;
-  const int p = p0 + tid;
-  const int s = tri_root_dev(p);
-  const int i = p - s * (s + 1) / 2;
-  const int j = s - i;
-  const int s_lo = tri_root_dev(p0);
-  const int ws = max(0, p0 - s_lo - 1);
-
-  const T *src[4] = {x + mi.off, x + nn + mi.off, x + 2 * nn + mi.off, kc + mi.off};
-  // byte offset (inside one window array) of this lane's 4-byte piece per
-  // round, and the window entry it starts (for the Dirichlet fix-up)
-  constexpr int RB = TPB * 4;                               // bytes per round
-  int es[ROUNDS], ei[ROUNDS];
-#pragma unroll
-  for (int r = 0; r < ROUNDS; ++r) {
-    const int q = ws + (r * RB + wave * 256 + lane * 4) / (int)sizeof(T);
-    const int sq = tri_root_dev(q);
-    es[r] = sq;
-    ei[r] = q - sq * (sq + 1) / 2;
-  }
-
-  auto issue = [&](int kk) {
-    const int ps = (int)tri(n + 1 - kk);
-    const int64_t base = plane_base(n, kk) + ws;
-    const int nbytes = max(0, min(wl, ps - ws)) * (int)sizeof(T);
-    T *slot = lds + (kk % NSLOT) * 4 * wl;
-#pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-      const int wb = r * RB + wave * 256;                   // wave-uniform
-      if (wb + lane * 4 < nbytes) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-          __builtin_amdgcn_global_load_lds(
-              reinterpret_cast<const char *>(src[a] + base) + wb + lane * 4,
-              (__attribute__((address_space(3))) void *)(reinterpret_cast<char *>(slot + a * wl) + wb),
-              4, 0, 0);
-      }
-    }
-  };
-  auto fix = [&](int kk) {                  // after this wave's loads landed
-    const int ps = (int)tri(n + 1 - kk);
-    T *slot = lds + (kk % NSLOT) * 4 * wl;
-#pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-      const int off = r * RB + wave * 256 + lane * 4;
-      if (off % (int)sizeof(T) != 0) continue;
-      const int e = off / (int)sizeof(T);
-      if (e >= wl || ws + e >= ps) continue;
-      const int z = zero_set(ei[r], es[r] - ei[r], kk, n);
-      if ((mi.dmask >> z) & 1u) {
-        slot[e] = T(0);
-        slot[wl + e] = T(0);
-        slot[2 * wl + e] = T(0);
-      }
-    }
-  };
-  auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
-
-  issue(w.ka - 1);
-  issue(w.ka);
-  issue(w.ka + 1);
-  wait_loads();
-  fix(w.ka - 1);
-  fix(w.ka);
-  fix(w.ka + 1);
-  __syncthreads();
-  const int e0 = p - ws;
-  const bool col_ok = (s >= 2) && (i >= 1) && (j >= 1);
-
-  for (int kk = w.ka; kk < w.kb; ++kk) {
-    const bool more = kk + 2 <= w.kb;
-    if (more) issue(kk + 2);
-    if (col_ok && s + kk <= n - 1) {
-      const T *Lm = lds + ((kk + NSLOT - 1) % NSLOT) * 4 * wl + e0;   // plane kk-1
-      const T *L0 = lds + (kk % NSLOT) * 4 * wl + e0;
-      const T *Lp = lds + ((kk + 1) % NSLOT) * 4 * wl + e0;
-      auto rd = [&](const T *L, int o) { return Node4<T>{L[o], L[wl + o], L[2 * wl + o], L[3 * wl + o]}; };
-      const Node4<T> c = rd(L0, 0);
-      Node4<T> nb[NDIR];
-#pragma unroll
-      for (int d = 0; d < NDIR; ++d)
-        nb[d] = rd(DIR_K[d] > 0 ? Lp : (DIR_K[d] < 0 ? Lm : L0), dir_a(d) + dir_b(d) * s);
-      // LDS reads and the scalar loads of the stencil constants share one
-      // wait counter: take all neighbour values before any constant load
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-      __builtin_amdgcn_sched_barrier(0);
-      T y0, y1, y2;
-      node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
-      const int64_t g = mi.off + plane_base(n, kk) + p;
-      if constexpr (RESID) {
-        y0 = f[g] - y0;
-        y1 = f[g + nn] - y1;
-        y2 = f[g + 2 * nn] - y2;
-      }
-      y[g] = y0;
-      y[g + nn] = y1;
-      y[g + 2 * nn] = y2;
-    }
-    wait_loads();
-    if (more) fix(kk + 2);
-    __syncthreads();
-  }
-}
-
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int ROUNDS>
-int launch_interior_dma(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
-  constexpr int TPB = 256;
-  const int wl = ROUNDS * TPB * 4 / (int)sizeof(T);        // window entries per array
-  const size_t lds = (size_t)NSLOT * 4 * wl * sizeof(T);
-  auto kern = k_interior_dma<T, METHOD, RESID, CORR, A0, ROUNDS, TPB>;
-  if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
-  hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
-                     ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
-  HHG_HIP(hipGetLastError());
-  return HHG_OK;
-}
-
 template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
 int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
   const int wl = h->wl_max;
@@ -463,25 +324,14 @@ int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hip
   return HHG_OK;
 }
 
-// Positions per work item (= threads): 256; window entries per thread in the
-// register-staged fallback: up to 2 (levels <= 7) or up to 6 (levels 8, 9).
+// Positions per work item (= threads): 256; window entries per thread: up
+// to 2 (levels <= 7) or up to 6 (level 8).
 template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
 int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
   if (h->n_work == 0) return HHG_OK;
-  // LDS-DMA staging while its window ring fits 80 KB (two workgroups per CU)
-  if (h->chunk == 256 && h->stage_dma) {
-    const int rounds = (h->wl_max * (int)sizeof(T) + 1023) / 1024;
-    if (rounds <= 2) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 2>(h, x, k, f, y, st);
-    if (rounds <= 4) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 4>(h, x, k, f, y, st);
-    if (rounds <= 5) return launch_interior_dma<T, METHOD, RESID, CORR, A0, 5>(h, x, k, f, y, st);
-  }
   const int nw = (h->wl_max + 255) / 256;
-  if (h->chunk == 256) {
-    if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256, 1>(h, x, k, f, y, st);
-    if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256, 1>(h, x, k, f, y, st);
-  } else if (h->chunk == 512) {
-    if (nw <= 4) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 4, 256, 2>(h, x, k, f, y, st);
-  }
+  if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256, 1>(h, x, k, f, y, st);
+  if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256, 1>(h, x, k, f, y, st);
   return fail(HHG_EINVAL, "interior window larger than supported");
 }
 

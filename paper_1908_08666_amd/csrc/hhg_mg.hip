@@ -585,6 +585,337 @@ int check_opts(const hhg_mg_opts *o) {
   return HHG_OK;
 }
 
+
+// ------------------------------------------------ generalized Stokes (Sec. 5.2)
+// The divergence pair B, B^T, the stabilization c_l(p, q) = -h^2/12 (grad p,
+// grad q) and the lumped pressure mass of eqn. generalizedstokes, equal-order
+// P1 velocity and pressure.  Every term is a sum over the elements at a node:
+// on element t with volume |t| and constant gradients g_a of its vertices a,
+// int psi = |t| / 4, so
+//   (B u)_i       = -sum_t |t|/4 sum_a g_a . u_a
+//   (B^T p)_{i,l} = -sum_t |t|/4 (g_i)_l sum_a p_a
+//   (C p)_i       = -h^2/12 sum_t |t| sum_a (g_i . g_a) p_a
+//   mass_i        =  sum_t |t| / 4,   C_ii = -h^2/12 sum_t |t| g_i . g_i.
+// One thread per slot sums over the node's elements inside its macro (all
+// 24 for a macro-interior node); the copy groups then add the other macros'
+// shares.  Velocity entries of Dirichlet nodes are read as zero and B^T rows
+// of Dirichlet nodes are zero, as for the velocity operator.
+enum { SK_DIV = 0, SK_GRAD = 1, SK_STAB = 2, SK_MASS = 3, SK_CDIAG = 4 };
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_stokes_rows(const MacroInfo *__restrict__ minfo,
+                                                     const StrainConst *__restrict__ stc,
+                                                     const uint8_t *__restrict__ fl,
+                                                     const double *__restrict__ in,
+                                                     double *__restrict__ out, int64_t N, double cst) {
+  const int m = blockIdx.y;
+  const MacroInfo mi = minfo[m];
+  const int n = mi.n;
+  const int64_t ls = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ls >= macro_nodes(n)) return;
+  int i, j, k;
+  local_ijk(ls, n, i, j, k);
+  const int64_t slot = mi.off + ls;
+  const StrainConst &sc = stc[m];
+  int64_t nb[NDIR];
+  bool inb[NDIR];
+#pragma unroll
+  for (int d = 0; d < NDIR; ++d) {
+    const int a = i + DIR_I[d], b = j + DIR_J[d], c = k + DIR_K[d];
+    inb[d] = a >= 0 && b >= 0 && c >= 0 && a + b + c <= n;
+    nb[d] = inb[d] ? mi.off + local_slot(n, a, b, c) : slot;
+  }
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  for (int t = 0; t < NTET; ++t) {
+    const int v1 = TET_V[t][0], v2 = TET_V[t][1], v3 = TET_V[t][2];
+    if (!(inb[v1] && inb[v2] && inb[v3])) continue;
+    const int64_t vs[4] = {slot, nb[v1], nb[v2], nb[v3]};
+    if constexpr (MODE == SK_DIV) {
+      double s = 0.0;
+      for (int a = 0; a < 4; ++a) {
+        if (fl[vs[a]] & 1) continue;
+        for (int c = 0; c < 3; ++c) s += sc.grad[t][a][c] * in[c * N + vs[a]];
+      }
+      acc0 -= 0.25 * sc.vol * s;
+    } else if constexpr (MODE == SK_GRAD) {
+      const double ps = in[vs[0]] + in[vs[1]] + in[vs[2]] + in[vs[3]];
+      acc0 -= 0.25 * sc.vol * sc.grad[t][0][0] * ps;
+      acc1 -= 0.25 * sc.vol * sc.grad[t][0][1] * ps;
+      acc2 -= 0.25 * sc.vol * sc.grad[t][0][2] * ps;
+    } else if constexpr (MODE == SK_STAB) {
+      double s = 0.0;
+      for (int a = 0; a < 4; ++a) {
+        const double gg = sc.grad[t][0][0] * sc.grad[t][a][0] + sc.grad[t][0][1] * sc.grad[t][a][1] +
+                          sc.grad[t][0][2] * sc.grad[t][a][2];
+        s += gg * in[vs[a]];
+      }
+      acc0 += cst * sc.vol * s;
+    } else if constexpr (MODE == SK_CDIAG) {
+      acc0 += cst * sc.vol * (sc.grad[t][0][0] * sc.grad[t][0][0] + sc.grad[t][0][1] * sc.grad[t][0][1] +
+                              sc.grad[t][0][2] * sc.grad[t][0][2]);
+    } else {
+      acc0 += 0.25 * sc.vol;
+    }
+  }
+  if constexpr (MODE == SK_GRAD) {
+    const bool dz = fl[slot] & 1;
+    out[slot] = dz ? 0.0 : acc0;
+    out[N + slot] = dz ? 0.0 : acc1;
+    out[2 * N + slot] = dz ? 0.0 : acc2;
+  } else {
+    out[slot] = acc0;
+  }
+}
+
+// scalar sum over the copies of every group, written to all copies
+__global__ __launch_bounds__(256) void k_copy_sum1(const int64_t *__restrict__ ptr,
+                                                   const int64_t *__restrict__ slots, int64_t ng,
+                                                   double *__restrict__ v) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ptr[g], b = ptr[g + 1];
+    double s = 0.0;
+    for (int64_t q = a; q < b; ++q) s += v[slots[q]];
+    for (int64_t q = a; q < b; ++q) v[slots[q]] = s;
+  }
+}
+
+// partial sums of (a, b) over owner slots of scalar fields (pressure: every
+// node); b null reads as ones
+__global__ __launch_bounds__(256) void k_dot_owner(const double *__restrict__ a,
+                                                   const double *__restrict__ b,
+                                                   const uint8_t *__restrict__ fl, int64_t N,
+                                                   double *__restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (fl[i] & 2) s += a[i] * (b ? b[i] : 1.0);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// per block: max over unknown owner nodes of |u_i - v_i| and of |u_i| (2-norms)
+__global__ __launch_bounds__(256) void k_node_max2(const double *__restrict__ u,
+                                                   const double *__restrict__ v,
+                                                   const uint8_t *__restrict__ fl, int64_t N,
+                                                   double *__restrict__ part) {
+  __shared__ double sh[8];
+  double dm = 0.0, um = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if ((fl[i] & 3) == 2) {
+      const double d0 = u[i] - v[i], d1 = u[N + i] - v[N + i], d2 = u[2 * N + i] - v[2 * N + i];
+      dm = fmax(dm, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+      um = fmax(um, sqrt(u[i] * u[i] + u[N + i] * u[N + i] + u[2 * N + i] * u[2 * N + i]));
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    dm = fmax(dm, __shfl_down(dm, off, 64));
+    um = fmax(um, __shfl_down(um, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = dm;
+    sh[4 + (threadIdx.x >> 6)] = um;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    part[2 * blockIdx.x + 1] = fmax(fmax(sh[4], sh[5]), fmax(sh[6], sh[7]));
+  }
+}
+
+// p += omega_p (B u + C p - g) / S;  rp = B u + C p - g kept for the caller
+__global__ void k_pressure_step(double *__restrict__ p, const double *__restrict__ rp,
+                                const double *__restrict__ S, double omega_p, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    p[s] += omega_p * rp[s] / S[s];
+}
+
+// a += c b (n entries)
+__global__ void k_axpy(double *__restrict__ a, const double *__restrict__ b, double c, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    a[s] = fma(c, b[s], a[s]);
+}
+
+// out = a + b - c (n entries; b or c may be null)
+__global__ void k_add3(double *__restrict__ out, const double *__restrict__ a, const double *__restrict__ b,
+                       const double *__restrict__ c, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    out[s] = a[s] + (b ? b[s] : 0.0) - (c ? c[s] : 0.0);
+}
+
+// S = mass / mu - diag(C): diagonal approximation of the pressure Schur
+// complement B A(mu)^-1 B^T - C
+__global__ void k_schur(double *__restrict__ S, const double *__restrict__ mass,
+                        const double *__restrict__ mu, const double *__restrict__ cdiag, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    S[s] = mass[s] / mu[s] - cdiag[s];
+}
+
+int stokes_rows(hhg_ctx *h, int op, double hl, const double *in, double *out, hipStream_t st) {
+  const double cst = -hl * hl / 12.0;
+  const dim3 g = macro_grid(h);
+  switch (op) {
+    case SK_DIV:
+      hipLaunchKernelGGL(k_stokes_rows<SK_DIV>, g, dim3(256), 0, st, h->d_minfo, h->d_stc, h->d_flags,
+                         in, out, h->n_nodes, cst);
+      break;
+    case SK_GRAD:
+      hipLaunchKernelGGL(k_stokes_rows<SK_GRAD>, g, dim3(256), 0, st, h->d_minfo, h->d_stc, h->d_flags,
+                         in, out, h->n_nodes, cst);
+      break;
+    case SK_STAB:
+      hipLaunchKernelGGL(k_stokes_rows<SK_STAB>, g, dim3(256), 0, st, h->d_minfo, h->d_stc,
+                         h->d_flags, in, out, h->n_nodes, cst);
+      break;
+    case SK_CDIAG:
+      hipLaunchKernelGGL(k_stokes_rows<SK_CDIAG>, g, dim3(256), 0, st, h->d_minfo, h->d_stc,
+                         h->d_flags, in, out, h->n_nodes, cst);
+      break;
+    default:
+      hipLaunchKernelGGL(k_stokes_rows<SK_MASS>, g, dim3(256), 0, st, h->d_minfo, h->d_stc,
+                         h->d_flags, in, out, h->n_nodes, cst);
+  }
+  HHG_HIP(hipGetLastError());
+  if (h->n_agrp > 0) {
+    if (op == SK_GRAD)
+      hipLaunchKernelGGL(k_copy_sum3<double>, grid1(h->n_agrp), dim3(256), 0, st, h->d_agrp_ptr,
+                         h->d_agrp_slot, h->n_agrp, out, h->n_nodes);
+    else
+      hipLaunchKernelGGL(k_copy_sum1, grid1(h->n_agrp), dim3(256), 0, st, h->d_agrp_ptr,
+                         h->d_agrp_slot, h->n_agrp, out);
+    HHG_HIP(hipGetLastError());
+  }
+  return HHG_OK;
+}
+
+// Stokes workspace: vectors on the finest level
+struct StokesWork {
+  double *ru, *z, *gp, *rp, *bu, *S, *mass, *cdiag, *uprev, *visc, *part;
+};
+size_t stokes_layout(const hhg_ctx *h, char *base, StokesWork *w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+    off += al256(bytes);
+    return p;
+  };
+  const size_t N = (size_t)h->n_nodes;
+  StokesWork tmp;
+  StokesWork &W = w ? *w : tmp;
+  W.ru = take(24 * N);
+  W.z = take(24 * N);
+  W.gp = take(24 * N);
+  W.rp = take(8 * N);
+  W.bu = take(8 * N);
+  W.S = take(8 * N);
+  W.mass = take(8 * N);
+  W.cdiag = take(8 * N);
+  W.uprev = take(24 * N);
+  W.visc = take(80 * N);
+  W.part = take(16 * MG_RED);
+  return off;
+}
+
+double host_sum(const double *part, int n, int stride = 1, int at = 0) {
+  double s = 0.0;
+  for (int q = 0; q < n; ++q) s += part[stride * q + at];
+  return s;
+}
+
+// sum over owner slots of a b (scalar fields), synchronous
+int dot_owner(hhg_ctx *h, const double *a, const double *b, double *part, hipStream_t st, double &out) {
+  hipLaunchKernelGGL(k_dot_owner, dim3(MG_RED), dim3(256), 0, st, a, b, h->d_flags, h->n_nodes, part);
+  HHG_HIP(hipGetLastError());
+  std::vector<double> hp(MG_RED);
+  HHG_HIP(hipMemcpyAsync(hp.data(), part, MG_RED * sizeof(double), hipMemcpyDeviceToHost, st));
+  HHG_HIP(hipStreamSynchronize(st));
+  out = host_sum(hp.data(), MG_RED);
+  return HHG_OK;
+}
+
+// sum over unknown owner slots of a . b (velocity fields), synchronous
+int dot_vel(hhg_ctx *h, const double *a, const double *b, double *part, hipStream_t st, double &out) {
+  hipLaunchKernelGGL(k_dot, dim3(MG_RED), dim3(256), 0, st, a, b, h->d_flags, h->n_nodes, part);
+  HHG_HIP(hipGetLastError());
+  std::vector<double> hp(MG_RED);
+  HHG_HIP(hipMemcpyAsync(hp.data(), part, MG_RED * sizeof(double), hipMemcpyDeviceToHost, st));
+  HHG_HIP(hipStreamSynchronize(st));
+  out = host_sum(hp.data(), MG_RED);
+  return HHG_OK;
+}
+
+// a += c (n entries)
+__global__ void k_add_const(double *__restrict__ a, double c, int64_t n) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x)
+    a[s] += c;
+}
+
+// Inexact Uzawa iteration on the finest level (see hhg_mg_stokes_solve):
+//   u <- u + V(f - A u - B^T p)
+//   p <- p + omega_p (B u + C p - g) / S,  S = mass / mu
+//   p <- p - (mass . p) / (mass . 1)
+// until the residual 2-norm of both blocks is <= tol_abs or maxit steps.
+// On return S.ru and S.rp hold the residuals of the final iterate.
+int uzawa(hhg_mg_s *mg, const MgWork &W, const StokesWork &S, const hhg_stokes_opts &o, double hl,
+          const double *f, const double *g, double *u, double *p, int maxit, double tol_abs,
+          hipStream_t st, int &iters, double &res) {
+  const int F = (int)mg->lev.size() - 1;
+  hhg_ctx *h = mg->lev[F];
+  const int64_t N = h->n_nodes;
+  hhg_mg_opts mo{};
+  mo.nu1 = o.nu1;
+  mo.nu2 = o.nu2;
+  mo.omega = o.omega;
+  mo.method = HHG_MG_CYCLE;
+  mo.precision = HHG_F64;
+  int rc;
+  double mtot = 0.0;
+  if ((rc = dot_owner(h, S.mass, nullptr, S.part, st, mtot))) return rc;
+  auto residuals = [&]() -> int {
+    int r2 = stokes_rows(h, SK_GRAD, hl, p, S.gp, st);
+    if (r2) return r2;
+    if ((r2 = apply_internal(h, HHG_F64, mg->method, f, u, W.k[F], S.ru, st))) return r2;  // f - A u
+    hipLaunchKernelGGL(k_axpy, grid1(3 * N), dim3(256), 0, st, S.ru, S.gp, -1.0, 3 * N);
+    if ((r2 = stokes_rows(h, SK_DIV, hl, u, S.bu, st))) return r2;
+    if ((r2 = stokes_rows(h, SK_STAB, hl, p, S.rp, st))) return r2;
+    hipLaunchKernelGGL(k_add3, grid1(N), dim3(256), 0, st, S.rp, S.rp, S.bu, g, N);  // B u + C p - g
+    HHG_HIP(hipGetLastError());
+    double a = 0.0, b = 0.0;
+    if ((r2 = dot_vel(h, S.ru, S.ru, S.part, st, a))) return r2;
+    if ((r2 = dot_owner(h, S.rp, S.rp, S.part, st, b))) return r2;
+    res = std::sqrt(a + b);
+    return HHG_OK;
+  };
+  if ((rc = residuals())) return rc;
+  iters = 0;
+  while (iters < maxit && !(res <= tol_abs)) {
+    if (!std::isfinite(res)) return fail(HHG_EBREAKDOWN, "non-finite Uzawa residual");
+    ++iters;
+    if ((rc = finest_cycle(mg, W, mo, S.ru, S.z, st))) return rc;     // z = V(f - A u - B^T p)
+    hipLaunchKernelGGL(k_axpy, grid1(3 * N), dim3(256), 0, st, u, S.z, 1.0, 3 * N);
+    if ((rc = stokes_rows(h, SK_DIV, hl, u, S.bu, st))) return rc;
+    if ((rc = stokes_rows(h, SK_STAB, hl, p, S.rp, st))) return rc;
+    hipLaunchKernelGGL(k_add3, grid1(N), dim3(256), 0, st, S.rp, S.rp, S.bu, g, N);
+    hipLaunchKernelGGL(k_pressure_step, grid1(N), dim3(256), 0, st, p, S.rp, S.S, o.omega_p, N);
+    HHG_HIP(hipGetLastError());
+    double mp = 0.0;
+    if ((rc = dot_owner(h, S.mass, p, S.part, st, mp))) return rc;
+    hipLaunchKernelGGL(k_add_const, grid1(N), dim3(256), 0, st, p, -mp / mtot, N);
+    HHG_HIP(hipGetLastError());
+    if ((rc = residuals())) return rc;
+  }
+  if (!std::isfinite(res)) return fail(HHG_EBREAKDOWN, "non-finite Uzawa residual");
+  return HHG_OK;
+}
+
 }  // namespace
 }  // namespace hhg
 
@@ -883,12 +1214,178 @@ done:
   if ((rc = apply_internal(h, HHG_F64, mg->method, b, x, W.k[F], W.pr, st))) return rc;
   if ((rc = dot(mg, W, W.pr, W.pr, &rr, st))) return rc;
   info->iterations = it;
+  info->iterations_run = it;       // checked every iteration
   info->outer_iterations = 1;
   info->status = status;
   info->rel_residual = nb > 0.0 ? std::sqrt(rr) / nb : 0.0;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (status == HHG_ENOCONV) return fail(HHG_ENOCONV, "multigrid solve reached maxit");
   if (status == HHG_EBREAKDOWN) return fail(HHG_EBREAKDOWN, "multigrid solve breakdown");
+  return HHG_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int hhg_stokes_rows(hhg_handle h, int32_t op, double hl, const double *in, double *out,
+                    void *stream) {
+  if (!h || !out || (op != HHG_STOKES_MASS && !in)) return fail(HHG_EINVAL, "null argument");
+  if (op < HHG_STOKES_DIV || op > HHG_STOKES_MASS) return fail(HHG_EINVAL, "unknown Stokes term");
+  if (op == HHG_STOKES_STAB && !(hl > 0.0)) return fail(HHG_EINVAL, "mesh width must be > 0");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(HHG_EINVAL, "misaligned pointer");
+  if (in == out) return fail(HHG_EINVAL, "out must not alias in");
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  return stokes_rows(h, op, hl, in, out, (hipStream_t)stream);
+}
+
+int hhg_mg_stokes_workspace_bytes(hhg_mg mg, size_t *bytes) {
+  const int rc = check_mg(mg);
+  if (rc) return rc;
+  if (!bytes) return fail(HHG_EINVAL, "null argument");
+  *bytes = stokes_layout(mg->lev.back(), nullptr, nullptr);
+  return HHG_OK;
+}
+
+namespace {
+int check_stokes(hhg_mg mg, const hhg_stokes_opts *o, const double *f, const double *u,
+                 const double *p, const double *mu, void *mgw, void *sw) {
+  int rc = check_mg(mg);
+  if (rc) return rc;
+  if (!o || !f || !u || !p || !mu || !mgw || !sw) return fail(HHG_EINVAL, "null argument");
+  if (((uintptr_t)f | (uintptr_t)u | (uintptr_t)p | (uintptr_t)mu) & 15 || ((uintptr_t)mgw | (uintptr_t)sw) & 255)
+    return fail(HHG_EINVAL, "misaligned pointer");
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 64 || o->nu2 > 64)
+    return fail(HHG_EINVAL, "smoothing steps must be 0..64 each, at least one in total");
+  if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(HHG_EINVAL, "omega must lie in (0, 2)");
+  if (!(o->omega_p > 0.0 && o->omega_p < 4.0)) return fail(HHG_EINVAL, "omega_p must lie in (0, 4)");
+  if (!(o->rtol >= 0.0) || o->maxit < 0) return fail(HHG_EINVAL, "rtol must be >= 0 and maxit >= 0");
+  return HHG_OK;
+}
+double mesh_width_of(const hhg_mg_s *mg, const hhg_stokes_opts *o) {
+  return o->h > 0.0 ? o->h : 1.0 / (double)(1 << mg->fine_level);
+}
+}  // namespace
+
+int hhg_mg_stokes_solve(hhg_mg mg, const hhg_stokes_opts *o, const double *f, const double *g,
+                        const double *mu, double *u, double *p, void *mg_workspace,
+                        void *stokes_workspace, hhg_solve_info *info, void *stream) {
+  int rc = check_stokes(mg, o, f, u, p, mu, mg_workspace, stokes_workspace);
+  if (rc) return rc;
+  if (!info) return fail(HHG_EINVAL, "null argument");
+  if ((uintptr_t)g & 15) return fail(HHG_EINVAL, "misaligned pointer");
+  if (mg_workspace != mg->ready)
+    return fail(HHG_EINVAL, "call hhg_mg_setup_coefficient with this workspace first");
+  if ((rc = mg_device(mg))) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  *info = hhg_solve_info{};
+  hipStream_t st = (hipStream_t)stream;
+  MgWork W;
+  layout(mg, static_cast<char *>(mg_workspace), &W);
+  StokesWork S;
+  stokes_layout(mg->lev.back(), static_cast<char *>(stokes_workspace), &S);
+  hhg_ctx *h = mg->lev.back();
+  const int64_t N = h->n_nodes;
+  const double hl = mesh_width_of(mg, o);
+  if ((rc = stokes_rows(h, SK_MASS, hl, nullptr, S.mass, st))) return rc;
+  if ((rc = stokes_rows(h, SK_CDIAG, hl, nullptr, S.cdiag, st))) return rc;
+  hipLaunchKernelGGL(k_schur, grid1(N), dim3(256), 0, st, S.S, S.mass, mu, S.cdiag, N);
+  HHG_HIP(hipGetLastError());
+  double ff = 0.0, gg = 0.0;
+  if ((rc = dot_vel(h, f, f, S.part, st, ff))) return rc;
+  if (g && (rc = dot_owner(h, g, g, S.part, st, gg))) return rc;
+  const double nrm = std::sqrt(ff + gg);
+  int it = 0;
+  double res = 0.0;
+  if ((rc = uzawa(mg, W, S, *o, hl, f, g, u, p, o->maxit, o->rtol * nrm, st, it, res))) return rc;
+  HHG_HIP(hipStreamSynchronize(st));
+  info->iterations = it;
+  info->iterations_run = it;
+  info->outer_iterations = 1;
+  info->rel_residual = nrm > 0.0 ? res / nrm : res;
+  info->status = info->rel_residual <= o->rtol ? HHG_OK : HHG_ENOCONV;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info->status == HHG_ENOCONV) return fail(HHG_ENOCONV, "Stokes solve reached maxit");
+  return HHG_OK;
+}
+
+int hhg_mg_stokes_picard(hhg_mg mg, const hhg_stokes_opts *o, const hhg_carreau *law,
+                         int32_t method, int32_t max_picard, const double *f, double *u,
+                         double *p, double *mu, void *mg_workspace, void *stokes_workspace,
+                         hhg_picard_info *info, void *stream) {
+  int rc = check_stokes(mg, o, f, u, p, mu, mg_workspace, stokes_workspace);
+  if (rc) return rc;
+  if (!law || !info) return fail(HHG_EINVAL, "null argument");
+  if (method != HHG_METHOD_SCALED && method != HHG_METHOD_ONTHEFLY)
+    return fail(HHG_EINVAL, "unknown operator method");
+  if (max_picard < 1) return fail(HHG_EINVAL, "max_picard must be >= 1");
+  if ((rc = mg_device(mg))) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  *info = hhg_picard_info{};
+  hipStream_t st = (hipStream_t)stream;
+  MgWork W;
+  layout(mg, static_cast<char *>(mg_workspace), &W);
+  StokesWork S;
+  stokes_layout(mg->lev.back(), static_cast<char *>(stokes_workspace), &S);
+  hhg_ctx *h = mg->lev.back();
+  const int64_t N = h->n_nodes;
+  const double hl = mesh_width_of(mg, o);
+  // mu = mu(u) and the velocity multigrid of A(mu)
+  auto viscosity = [&](bool setup) -> int {
+    int r2 = hhg_nodal_viscosity(h, u, law, mu, S.visc, st);
+    if (r2) return r2;
+    if (!setup) return HHG_OK;
+    if ((r2 = hhg_mg_setup_coefficient(mg, method, mu, mg_workspace, st))) return r2;
+    hipLaunchKernelGGL(k_schur, grid1(N), dim3(256), 0, st, S.S, S.mass, mu, S.cdiag, N);
+    HHG_HIP(hipGetLastError());
+    return HHG_OK;
+  };
+  hipLaunchKernelGGL(k_fill0<double>, grid1(3 * N), dim3(256), 0, st, u, 3 * N);
+  hipLaunchKernelGGL(k_fill0<double>, grid1(N), dim3(256), 0, st, p, N);
+  HHG_HIP(hipGetLastError());
+  if ((rc = stokes_rows(h, SK_MASS, hl, nullptr, S.mass, st))) return rc;
+  if ((rc = stokes_rows(h, SK_CDIAG, hl, nullptr, S.cdiag, st))) return rc;
+  if ((rc = viscosity(true))) return rc;
+  double ff = 0.0;
+  if ((rc = dot_vel(h, f, f, S.part, st, ff))) return rc;
+  const double nrm = std::sqrt(ff);
+  int status = HHG_ENOCONV;
+  std::vector<double> hp(2 * MG_RED);
+  for (int n = 0; n < max_picard; ++n) {
+    HHG_HIP(hipMemcpyAsync(S.uprev, u, 24 * (size_t)N, hipMemcpyDeviceToDevice, st));
+    int it = 0;
+    double res = 0.0;
+    if ((rc = uzawa(mg, W, S, *o, hl, f, nullptr, u, p, 1, 0.0, st, it, res))) return rc;
+    if ((rc = viscosity(true))) return rc;
+    info->picard = n + 1;
+    hipLaunchKernelGGL(k_node_max2, dim3(MG_RED), dim3(256), 0, st, u, S.uprev, h->d_flags, N, S.part);
+    HHG_HIP(hipGetLastError());
+    HHG_HIP(hipMemcpyAsync(hp.data(), S.part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HHG_HIP(hipStreamSynchronize(st));
+    double dm = 0.0, um = 0.0;
+    for (int q = 0; q < MG_RED; ++q) {
+      dm = std::max(dm, hp[2 * q]);
+      um = std::max(um, hp[2 * q + 1]);
+    }
+    info->rel_change = um > 0.0 ? dm / um : 0.0;
+    if (!std::isfinite(info->rel_change)) return fail(HHG_EBREAKDOWN, "non-finite fixed-point iterate");
+    if (dm < 1e-3 * um) {
+      status = HHG_OK;
+      break;
+    }
+  }
+  int it = 0;
+  double res = 0.0;
+  if ((rc = uzawa(mg, W, S, *o, hl, f, nullptr, u, p, o->maxit, o->rtol * nrm, st, it, res))) return rc;
+  info->final_iterations = it;
+  info->rel_residual = nrm > 0.0 ? res / nrm : res;
+  if (info->rel_residual > o->rtol) status = HHG_ENOCONV;
+  if ((rc = viscosity(false))) return rc;
+  HHG_HIP(hipStreamSynchronize(st));
+  info->status = status;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status == HHG_ENOCONV) return fail(HHG_ENOCONV, "fixed-point or final Stokes iteration reached its limit");
   return HHG_OK;
 }
 

@@ -253,13 +253,14 @@ int build_macro_tables(const double *V, int n, const hhg_op_desc &op, MacroTable
       }
     const int ix[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
     for (int q = 0; q < 6; ++q) {
-      sc.shat[p][q] = Ssym[d][ix[q][0]][ix[q][1]];
-      sc.a0[p][q] = 0.5 * (A0[d][ix[q][0]][ix[q][1]] + A0[d][ix[q][1]][ix[q][0]]);
+      sc.pr[p].shat[q] = Ssym[d][ix[q][0]][ix[q][1]];
+      sc.pr[p].a0[q] = 0.5 * (A0[d][ix[q][0]][ix[q][1]] + A0[d][ix[q][1]][ix[q][0]]);
     }
   }
   sc.has_a0 = any_a0 ? 1 : 0;
   // correction blocks C^v_d = 1/4 (antisym of the two elements containing v)
   if (op.corr == HHG_CORR_PHYSICAL) {
+    double cax[NDIR][3][3] = {};
     for (int d = 0; d < NDIR; ++d) {
       const int np = DIR_NT[d] == 6 ? 3 : 2;
       for (int q = 0; q < np; ++q) {
@@ -281,11 +282,22 @@ int build_macro_tables(const double *V, int n, const hhg_op_desc &op, MacroTable
         }
         if (cnt != 2) return fail(HHG_EINVAL, "ring node not in exactly two edge elements");
         // y = C x = c cross x with c = (C[2][1], C[0][2], C[1][0])
-        sc.cax[d][q][0] = C[2][1];
-        sc.cax[d][q][1] = C[0][2];
-        sc.cax[d][q][2] = C[1][0];
+        cax[d][q][0] = C[2][1];
+        cax[d][q][1] = C[0][2];
+        cax[d][q][2] = C[1][0];
       }
     }
+    double cscale = 0.0;
+    for (int d = 0; d < NDIR; ++d)
+      for (int q = 0; q < 3; ++q)
+        for (int c = 0; c < 3; ++c) cscale = std::max(cscale, std::fabs(cax[d][q][c]));
+    for (int p = 0; p < NPAIR; ++p)
+      for (int q = 0; q < 3; ++q)
+        for (int c = 0; c < 3; ++c) {
+          if (std::fabs(cax[2 * p][q][c] - cax[2 * p + 1][q][c]) > 1e-12 * (cscale > 0 ? cscale : 1.0))
+            return fail(HHG_EINVAL, "correction blocks differ between d and -d");
+          sc.pr[p].cax[q][c] = cax[2 * p][q][c];
+        }
   }
   // k-hat weights: ring node v is in 2 of the |T_d| elements, each element
   // mean weighs its vertices 1/4 (eq. nodalquad), the patch mean 1/|T_d|
@@ -310,14 +322,14 @@ int64_t tri_root(int64_t p) {  // largest s with s(s+1)/2 <= p
 
 template <typename TO>
 void convert(const StencilConst<double> &a, StencilConst<TO> &b) {
-  for (int p = 0; p < NPAIR; ++p)
+  for (int p = 0; p < NPAIR; ++p) {
     for (int q = 0; q < 6; ++q) {
-      b.shat[p][q] = (TO)a.shat[p][q];
-      b.a0[p][q] = (TO)a.a0[p][q];
+      b.pr[p].shat[q] = (TO)a.pr[p].shat[q];
+      b.pr[p].a0[q] = (TO)a.pr[p].a0[q];
     }
-  for (int d = 0; d < NDIR; ++d)
     for (int q = 0; q < 3; ++q)
-      for (int c = 0; c < 3; ++c) b.cax[d][q][c] = (TO)a.cax[d][q][c];
+      for (int c = 0; c < 3; ++c) b.pr[p].cax[q][c] = (TO)a.pr[p].cax[q][c];
+  }
   b.w_end = (TO)a.w_end;
   b.w_ring6 = (TO)a.w_ring6;
   b.w_ring4 = (TO)a.w_ring4;
@@ -415,7 +427,7 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   for (int m = 0; m < M; ++m) {
     const int L = mesh->level[m];
     if (L < MIN_LEVEL || L > MAX_LEVEL)
-      return fail(HHG_EINVAL, "level of macro " + std::to_string(m) + " outside 2..9");
+      return fail(HHG_EINVAL, "level of macro " + std::to_string(m) + " outside 2..8");
     if (mesh->coupling == HHG_CONFORMING && L != mesh->level[0])
       return fail(HHG_EINVAL, "conforming macros need one common level");
     const double *V = mesh->verts + 12 * m;
@@ -648,12 +660,6 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   if (env) h->planes_per_item = std::max(1, std::atoi(env));
   const char *envs = std::getenv("HHG_SERIAL_APPLY");
   h->serial_apply = envs && std::atoi(envs) == 1;
-  const char *envd = std::getenv("HHG_STAGE_DMA");
-  h->stage_dma = envd && std::atoi(envd) == 1;
-  // positions per interior work item: 256 (one per thread) or 512 (two per
-  // thread: a smaller halo per position and more rows per barrier)
-  const char *envc = std::getenv("HHG_CHUNK");
-  h->chunk = (envc && std::atoi(envc) == 512) ? 512 : 256;
   {
     std::vector<int> all(M);
     for (int m = 0; m < M; ++m) all[m] = m;
@@ -672,31 +678,89 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
 
 }  // namespace
 
+namespace {
+// Workgroups an interior launch keeps resident on an MI355X: 256 compute
+// units, three FP64 interior workgroups each (LDS and registers).
+constexpr int RESIDENT_ITEMS = 768;
+// Cost of one plane step of a chunk in units of one wave's row: the waves
+// whose lowest anti-diagonal still has an interior row in plane k, plus the
+// step's staging and barrier.
+constexpr int STEP_OVERHEAD = 2;
+int64_t step_cost(int n, int64_t p0, int CH, int k) {
+  const int64_t npos = tri(n - 1);
+  int64_t c = STEP_OVERHEAD;
+  for (int64_t q = p0; q < std::min<int64_t>(p0 + CH, npos); q += 64)
+    if (tri_root(q) + k <= n - 1) ++c;
+  return c;
+}
+}  // namespace
+
 void build_work(const hhg_ctx *h, const std::vector<int> &macros, const int *slab,
                 std::vector<WorkItem> &out, int &wl_max) {
   const int CH = h->chunk;
   std::vector<WorkItem> natural;
   wl_max = 0;
+  struct Column {
+    int m, c, kmax, depth;
+    std::vector<int64_t> cost;   // per plane 1..kmax (balanced columns)
+  };
+  std::vector<Column> cols;
+  int64_t total_cost = 0;
   for (int m : macros) {
     const int n = h->minfo[m].n;
     const int lev = h->minfo[m].level;
-    const int depth = std::max(1, (slab && slab[lev] > 0) ? slab[lev] : default_slab(h, lev));
+    const int sl = (slab && slab[lev] != 0) ? slab[lev] : default_slab(h, lev);
+    const int depth = sl == SLAB_BALANCED ? 0 : std::max(1, sl);
     const int64_t npos = tri(n - 1);  // interior positions live below T(n-1)
     const int nchunk = (int)((npos + CH - 1) / CH);
-    std::vector<int> kmax(nchunk);
-    int kmax_all = 0;
     for (int c = 0; c < nchunk; ++c) {
       const int64_t p0 = (int64_t)c * CH;
       const int64_t s_lo = tri_root(p0);
       const int64_t s_hi = std::min<int64_t>(tri_root(p0 + CH - 1), n - 2);
       const int64_t ws = std::max<int64_t>(0, p0 - s_lo - 1);
       wl_max = std::max<int>(wl_max, (int)(p0 + CH - 1 + s_hi + 2 - ws + 1));
-      kmax[c] = (int)(n - 1 - std::max<int64_t>(2, s_lo));
-      kmax_all = std::max(kmax_all, kmax[c]);
+      Column col{m, c, (int)(n - 1 - std::max<int64_t>(2, s_lo)), depth, {}};
+      if (depth == 0) {
+        col.cost.resize(col.kmax);
+        for (int k = 1; k <= col.kmax; ++k) {
+          col.cost[k - 1] = step_cost(n, p0, CH, k);
+          total_cost += col.cost[k - 1];
+        }
+      }
+      cols.push_back(std::move(col));
     }
-    for (int ka = 1; ka <= kmax_all; ka += depth)
-      for (int c = 0; c < nchunk; ++c)
-        if (ka <= kmax[c]) natural.push_back({m, c, ka, std::min(ka + depth, kmax[c] + 1)});
+  }
+  // fixed depth: slabs of `depth` planes, plane range by plane range (all
+  // chunks of a macro at the lowest planes first); balanced: every column
+  // cut into consecutive segments of about total / RESIDENT_ITEMS cost
+  const double target = std::max(1.0, (double)total_cost / RESIDENT_ITEMS);
+  size_t q0 = 0;
+  while (q0 < cols.size()) {
+    size_t q1 = q0;
+    while (q1 < cols.size() && cols[q1].m == cols[q0].m) ++q1;
+    int kmax_all = 0;
+    for (size_t q = q0; q < q1; ++q) kmax_all = std::max(kmax_all, cols[q].kmax);
+    for (size_t q = q0; q < q1; ++q) {
+      const Column &col = cols[q];
+      if (col.depth != 0) continue;
+      int ka = 1;
+      double acc = 0.0;
+      for (int k = 1; k <= col.kmax; ++k) {
+        acc += (double)col.cost[k - 1];
+        if (acc >= target || k == col.kmax) {
+          natural.push_back({col.m, col.c, ka, k + 1});
+          ka = k + 1;
+          acc = 0.0;
+        }
+      }
+    }
+    for (int ka = 1; ka <= kmax_all; ka += 1)
+      for (size_t q = q0; q < q1; ++q) {
+        const Column &col = cols[q];
+        if (col.depth == 0 || (ka - 1) % col.depth != 0) continue;
+        if (ka <= col.kmax) natural.push_back({col.m, col.c, ka, std::min(ka + col.depth, col.kmax + 1)});
+      }
+    q0 = q1;
   }
   // workgroup g runs on XCD g % NXCD: give every XCD a contiguous stretch of
   // the natural order so that neighbouring chunks share its L2

@@ -42,7 +42,7 @@ struct CGState {
   double alpha;
   double beta;
   int32_t bad;     // breakdown seen
-  int32_t pad;
+  int32_t bad_it;  // iteration of the current block in which it was first seen
   double hist[MAX_CHECK];  // (r, r) after each iteration of the current block
 };
 
@@ -198,9 +198,11 @@ __global__ __launch_bounds__(RED_TPB) void k_finalize(const double *__restrict__
     st->rho = s0;
     st->rr = s1;
     st->bad = (!isfinite(s0) || !isfinite(s1) || s0 < 0.0) ? 1 : 0;
+    st->bad_it = 0;
   } else if (mode == FIN_ALPHA) {
     st->pq = s0;
     if (!(s0 > 0.0) || !isfinite(s0)) {
+      if (!st->bad) st->bad_it = hidx;
       st->bad = 1;
       st->alpha = 0.0;
     } else {
@@ -214,7 +216,10 @@ __global__ __launch_bounds__(RED_TPB) void k_finalize(const double *__restrict__
     st->rho = s0;
     st->rr = s1;
     st->hist[hidx] = s1;
-    if (!isfinite(s0) || !isfinite(s1)) st->bad = 1;
+    if (!isfinite(s0) || !isfinite(s1)) {
+      if (!st->bad) st->bad_it = hidx;
+      st->bad = 1;
+    }
   } else {
     st->rr = s0;
   }
@@ -311,7 +316,7 @@ __global__ __launch_bounds__(256) void k_diag(const MacroInfo *__restrict__ minf
         for (int q = 0; q < np; ++q) ring += nk[RING_V[dd][q]] + nk[RING_VM[dd][q]];
         const double wr = DIR_NT[dd] == 6 ? sc.w_ring6 : sc.w_ring4;
         const double kh = sc.w_end * (kc0 + nk[dd]) + wr * ring;
-        for (int q = 0; q < 6; ++q) d[q] -= kh * sc.shat[dd >> 1][q] + sc.a0[dd >> 1][q];
+        for (int q = 0; q < 6; ++q) d[q] -= kh * sc.pr[dd >> 1].shat[q] + sc.pr[dd >> 1].a0[q];
       }
     } else {
       const ElemConst<double> &ec = ecs[m];
@@ -449,13 +454,17 @@ struct Host {
 
 // One preconditioned CG run on A x = b (type T) from the given x to
 // ||r|| <= tol_abs.  Returns HHG_OK / HHG_ENOCONV / HHG_EBREAKDOWN.
+// Iterations run in blocks of `check` between host checks: `run` counts
+// every iteration executed, `iters` the iterations until the recursive
+// residual first met tol_abs (= run when it never did).
 template <typename T>
 int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T *z, T *p, T *q,
         const T *P, double *part, CGState *dst, CGState *hst, double tol_abs, int maxit, int check,
-        hipStream_t st, int &iters) {
+        hipStream_t st, int &iters, int &run) {
   const int prec = sizeof(T) == 8 ? HHG_F64 : HHG_F32;
   const int64_t N = h->n_nodes;
   iters = 0;
+  run = 0;
   int rc = apply_internal(h, prec, method, b, x, k, r, st);  // r = b - A x
   if (rc) return rc;
   {
@@ -476,7 +485,7 @@ int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T
       ProfScope ps(h, HHG_K_SOLVER_VECTOR, st);
       hipLaunchKernelGGL(k_dot2<T>, dim3(RED_GRID), dim3(RED_TPB), 0, st, p, q, (const T *)nullptr,
                          (const T *)nullptr, h->d_flags, N, part);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst, FIN_ALPHA, 0);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst, FIN_ALPHA, it);
       if (flex)
         hipLaunchKernelGGL((k_update<T, true>), dim3(RED_GRID), dim3(RED_TPB), 0, st, x, p, r, q, P, z,
                            h->d_flags, N, dst, part);
@@ -509,8 +518,8 @@ int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T
     if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
   }
   int status = HHG_ENOCONV;
-  while (iters < maxit) {
-    const int nit = std::min(check, maxit - iters);
+  while (run < maxit) {
+    const int nit = std::min(check, maxit - run);
     if (use_graph && nit == check) {
       hipError_t e = hipGraphLaunch(exec, st);
       if (e != hipSuccess) {
@@ -526,18 +535,26 @@ int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T
     }
     HHG_HIP(hipMemcpyAsync(hst, dst, sizeof(CGState), hipMemcpyDeviceToHost, st));
     HHG_HIP(hipStreamSynchronize(st));
+    // the first iteration of the block that met the tolerance, if it came
+    // before a breakdown
+    const int last = hst->bad ? std::min(hst->bad_it, nit) : nit;
+    int first = -1;
+    for (int it = 0; it < last; ++it)
+      if (std::sqrt(hst->hist[it]) <= tol_abs) {
+        first = it;
+        break;
+      }
+    if (first >= 0) {
+      iters = run + first + 1;
+      run += nit;
+      status = HHG_OK;
+      break;
+    }
+    run += nit;
+    iters = run;
     if (hst->bad) {
       status = HHG_EBREAKDOWN;
       set_error("CG breakdown: p^T A p <= 0 or non-finite value");
-      iters += nit;
-      break;
-    }
-    bool done = false;
-    for (int it = 0; it < nit; ++it)
-      if (std::sqrt(hst->hist[it]) <= tol_abs) done = true;
-    iters += nit;
-    if (done) {
-      status = HHG_OK;
       break;
     }
   }
@@ -639,7 +656,7 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
   const double bnorm = std::sqrt(bb);
   if (!std::isfinite(bnorm)) return fail(HHG_EBREAKDOWN, "non-finite right-hand side");
   int status = HHG_OK;
-  int total = 0;
+  int total = 0, total_run = 0;
   if (bnorm == 0.0) {
     hipLaunchKernelGGL(k_fill<double>, grid_for(3 * N), dim3(256), 0, st, x, 0.0, 3 * N);
     HHG_HIP(hipStreamSynchronize(st));
@@ -651,12 +668,13 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
     double *z = at<double>(ws, L.off_z64), *p = at<double>(ws, L.off_p64), *q = at<double>(ws, L.off_q64);
     int outer = 0;
     status = HHG_ENOCONV;
-    while (total < o->maxit) {
-      int it = 0;
+    while (total_run < o->maxit) {
+      int it = 0, itr = 0;
       ++outer;
       rc = pcg<double>(h, o->method, o->solver == HHG_FCG_F64, b, k, x, r64, z, p, q, P64, part, dst, hst, o->rtol * bnorm,
-                       o->maxit - total, check, st, it);
+                       o->maxit - total_run, check, st, it, itr);
       total += it;
+      total_run += itr;
       if (rc == HHG_EBREAKDOWN || (rc != HHG_OK && rc != HHG_ENOCONV)) {
         status = rc;
         break;
@@ -670,7 +688,7 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
         status = HHG_OK;
         break;
       }
-      if (it == 0) break;
+      if (itr == 0) break;
     }
     info->outer_iterations = outer;
   } else {
@@ -696,15 +714,16 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
         status = HHG_OK;
         break;
       }
-      if (total >= o->maxit) break;
+      if (total_run >= o->maxit) break;
       ++outer;
       hipLaunchKernelGGL(k_cast64to32, grid_for(3 * N), dim3(256), 0, st, r64, b32, 3 * N);
       hipLaunchKernelGGL(k_fill<float>, grid_for(3 * N), dim3(256), 0, st, e32, 0.0f, 3 * N);
       HHG_HIP(hipGetLastError());
-      int it = 0;
+      int it = 0, itr = 0;
       rc = pcg<float>(h, o->method, false, b32, k32, e32, r32, z32, p32, q32, P32, part, dst, hst,
-                      o->inner_rtol * std::sqrt(rr), o->maxit - total, check, st, it);
+                      o->inner_rtol * std::sqrt(rr), o->maxit - total_run, check, st, it, itr);
       total += it;
+      total_run += itr;
       if (rc == HHG_EBREAKDOWN || (rc != HHG_OK && rc != HHG_ENOCONV)) {
         status = rc;
         break;
@@ -716,6 +735,7 @@ int solve_impl(hhg_ctx *h, const hhg_solve_opts *o, const double *b, const doubl
   }
   HHG_HIP(hipStreamSynchronize(st));
   info->iterations = total;
+  info->iterations_run = total_run;
   info->status = status;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (status == HHG_ENOCONV) set_error("maxit reached before rtol");

@@ -182,7 +182,8 @@ class Mesh:
         rc = self._lib.hhg_cg_solve(self._h, ctypes.byref(o), _dev_ptr(b, (3, N), torch.float64),
                                     _dev_ptr(k, (N,), torch.float64), _dev_ptr(x, (3, N), torch.float64),
                                     ws, ctypes.byref(info), _stream_ptr(stream))
-        out = dict(iterations=info.iterations, outer_iterations=info.outer_iterations,
+        out = dict(iterations=info.iterations, iterations_run=info.iterations_run,
+                   outer_iterations=info.outer_iterations,
                    status=L.STATUS_NAMES.get(info.status if rc == L.HHG_OK or info.status else rc, rc),
                    code=rc, rel_residual=info.rel_residual, seconds=info.seconds,
                    message=(self._lib.hhg_last_error() or b"").decode())
@@ -255,6 +256,24 @@ class Mesh:
 
     def graph_destroy(self, graph_id):
         L.check(self._lib.hhg_graph_destroy(self._h, int(graph_id)))
+
+    def stokes_rows(self, op, x=None, hl=0.0, out=None, stream=None):
+        """One term of the generalized Stokes system (``hhg_stokes_rows``):
+        op "div" (x [3, n] -> [n]), "grad" ([n] -> [3, n]), "stab" ([n] -> [n],
+        mesh width hl) or "mass" (-> [n])."""
+        import torch
+        code = {"div": L.HHG_STOKES_DIV, "grad": L.HHG_STOKES_GRAD, "stab": L.HHG_STOKES_STAB,
+                "mass": L.HHG_STOKES_MASS}[op]
+        N = self.n_nodes
+        in_shape = (3, N) if op == "div" else (N,)
+        out_shape = (3, N) if op == "grad" else (N,)
+        dev = x.device if x is not None else torch.device("cuda")
+        if out is None:
+            out = torch.empty(out_shape, dtype=torch.float64, device=dev)
+        px = _dev_ptr(x, in_shape, torch.float64) if x is not None else ctypes.c_void_p(0)
+        L.check(self._lib.hhg_stokes_rows(self._h, code, float(hl), px,
+                                          _dev_ptr(out, out_shape, torch.float64), _stream_ptr(stream)))
+        return out
 
     # ------------------------------------------------------------ tracing
     def profile_enable(self, on=True):
@@ -400,6 +419,76 @@ class Multigrid:
         if rc != L.HHG_OK and raise_on_status:
             L.check(rc)
         return x, out
+
+    # ------------------------------------------------ generalized Stokes
+    def _stokes_workspace(self, device):
+        import torch
+        n = ctypes.c_size_t()
+        L.check(self._lib.hhg_mg_stokes_workspace_bytes(self._mg, ctypes.byref(n)))
+        nb = int(n.value)
+        ws = getattr(self, "_sws", None)
+        if ws is None or ws.numel() < nb + 256 or ws.device != device:
+            self._sws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        base = self._sws.data_ptr()
+        return ctypes.c_void_p(base + ((-base) % 256))
+
+    @staticmethod
+    def _stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit):
+        return L.StokesOpts(int(nu1), int(nu2), float(omega), float(omega_p), float(h), float(rtol),
+                            int(maxit), 0)
+
+    def stokes_solve(self, f, mu, u=None, p=None, g=None, nu1=3, nu2=3, omega=0.7, omega_p=1.0,
+                     h=0.0, rtol=1e-8, maxit=500, stream=None, raise_on_status=True):
+        """Inexact Uzawa for the generalized Stokes system on the finest
+        level (``hhg_mg_stokes_solve``); call setup_coefficient(mu) first.
+        Returns (u, p, info dict)."""
+        import torch
+        fm = self.meshes[-1]
+        N = fm.n_nodes
+        if u is None:
+            u = torch.zeros((3, N), dtype=torch.float64, device=f.device)
+        if p is None:
+            p = torch.zeros((N,), dtype=torch.float64, device=f.device)
+        o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit)
+        info = L.SolveInfo()
+        gp = _dev_ptr(g, (N,), torch.float64) if g is not None else ctypes.c_void_p(0)
+        rc = self._lib.hhg_mg_stokes_solve(self._mg, ctypes.byref(o), _dev_ptr(f, (3, N), torch.float64), gp,
+                                           _dev_ptr(mu, (N,), torch.float64), _dev_ptr(u, (3, N), torch.float64),
+                                           _dev_ptr(p, (N,), torch.float64), self._workspace(f.device),
+                                           self._stokes_workspace(f.device), ctypes.byref(info),
+                                           _stream_ptr(stream))
+        out = dict(iterations=info.iterations, status=L.STATUS_NAMES.get(info.status, info.status),
+                   code=rc, rel_residual=info.rel_residual, seconds=info.seconds)
+        if rc != L.HHG_OK and raise_on_status:
+            L.check(rc)
+        return u, p, out
+
+    def stokes_picard(self, f, eta0, eta_inf, kappa, r, method="scaled", max_picard=100, nu1=3, nu2=3,
+                      omega=0.7, omega_p=1.0, h=0.0, rtol=1e-3, maxit=500, stream=None,
+                      raise_on_status=True):
+        """Fixed-point iteration for the Carreau fluid (``hhg_mg_stokes_picard``).
+        Returns (u, p, mu, info dict)."""
+        import torch
+        fm = self.meshes[-1]
+        N = fm.n_nodes
+        u = torch.empty((3, N), dtype=torch.float64, device=f.device)
+        p = torch.empty((N,), dtype=torch.float64, device=f.device)
+        mu = torch.empty((N,), dtype=torch.float64, device=f.device)
+        o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit)
+        law = L.Carreau(float(eta0), float(eta_inf), float(kappa), float(r))
+        m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
+        info = L.PicardInfo()
+        rc = self._lib.hhg_mg_stokes_picard(self._mg, ctypes.byref(o), ctypes.byref(law), m, int(max_picard),
+                                            _dev_ptr(f, (3, N), torch.float64), _dev_ptr(u, (3, N), torch.float64),
+                                            _dev_ptr(p, (N,), torch.float64), _dev_ptr(mu, (N,), torch.float64),
+                                            self._workspace(f.device), self._stokes_workspace(f.device),
+                                            ctypes.byref(info), _stream_ptr(stream))
+        out = dict(picard=info.picard, final_iterations=info.final_iterations,
+                   status=L.STATUS_NAMES.get(info.status, info.status), code=rc, rel_change=info.rel_change,
+                   rel_residual=info.rel_residual, seconds=info.seconds)
+        if rc != L.HHG_OK and raise_on_status:
+            L.check(rc)
+        return u, p, mu, out
 
     def close(self):
         for m in getattr(self, "meshes", []):

@@ -91,7 +91,7 @@ def test_setup_rejects_bad_input(bad):
     if bad == "level_low":
         lv = 1
     elif bad == "level_high":
-        lv = 10
+        lv = 9                      # above the largest level (8)
     elif bad == "mixed":
         lv = [3, 3, 3, 3, 3, 4]
     elif bad == "degenerate":

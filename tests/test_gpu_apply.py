@@ -218,3 +218,49 @@ def test_full_size_cube24_level7_sampled_rows():
     err = rel_err(y[rows], ref[rows])
     print(f"  cube24 level-7 sampled rows: {err:.3e}", flush=True)
     assert err <= TOL[torch.float64]
+
+
+def test_unit_tet_level8_sampled_rows():
+    """The largest level the library accepts: one macro at level 8 (257
+    points per edge, 2,862,209 nodes; the window of a 256-position chunk
+    needs up to 6 entries per thread).  Sampled rows of the scaled and the
+    on-the-fly operator in FP64 and FP32 against the oracle."""
+    lib, orc, s2n = setup_case(W.unit_tet(), 8, EFORM)
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(2, 0), 16, 1.0)
+    x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(2, 1)).reshape(-1, 3)
+    rows = np.unique(np.random.default_rng(13).choice(orc.unknown, 1000, replace=False))
+    for method in ("scaled", "onthefly"):
+        ref = oracle_apply(orc, k, EFORM, x, method, torch.float64, rows=rows)
+        ref32 = oracle_apply(orc, k, EFORM, x, method, torch.float32, rows=rows)
+        for dtype, want in ((torch.float64, ref), (torch.float32, ref32)):
+            y = gather_consistent(run_apply(lib, s2n, x, k, dtype, method), s2n, orc.n_nodes)
+            err = rel_err(y[rows], want[rows])
+            print(f"  level-8 sampled rows {method} {dtype}: {err:.3e}", flush=True)
+            assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("env", [dict(HHG_PLANES_PER_ITEM="1"), dict(HHG_PLANES_PER_ITEM="2"),
+                                 dict(HHG_PLANES_PER_ITEM="7"), dict(HHG_SERIAL_APPLY="1")])
+def test_environment_switches_bitwise(env, monkeypatch):
+    """The slab depth override and the one-stream apply (read when a handle
+    is set up) move rows between workgroups and streams only: the apply of
+    both operators is bitwise the default handle's, which the oracle checks."""
+    from paper_1908_08666_amd import Mesh
+    orc = MacroMesh(W.kuhn6(), 5)
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(2, 0), 16, 1.0)
+    x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(2, 1)).reshape(-1, 3)
+    base = Mesh(W.kuhn6(), 5, **EFORM)
+    for name, val in env.items():
+        monkeypatch.setenv(name, val)
+    other = Mesh(W.kuhn6(), 5, **EFORM)
+    for name in env:
+        monkeypatch.delenv(name)
+    s2n = slot_to_node(base, orc)
+    for method in ("scaled", "onthefly"):
+        for dtype in (torch.float64, torch.float32):
+            a = run_apply(base, s2n, x, k, dtype, method)
+            b = run_apply(other, s2n, x, k, dtype, method)
+            assert np.array_equal(a, b), (env, method, dtype)
+    y = gather_consistent(run_apply(other, s2n, x, k, torch.float64), s2n, orc.n_nodes)
+    ref = oracle_apply(orc, k, EFORM, x, "scaled", torch.float64)
+    assert rel_err(y[orc.unknown], ref[orc.unknown]) <= TOL[torch.float64]

@@ -71,7 +71,7 @@ def test_uneven_levels_parity_and_tuning_invariance(dtype):
     assert np.all(y_nodes[orc.dirichlet] == 0)
     # tuning moves rows between workgroups only: bitwise identical results
     for slabs, grid in (([1, 1, 1], 0), ([2, 8, 32], 0), ([64, 64, 64], 0), ([4, 4, 4], 256),
-                        ([1, 2, 4], 8), ([8, 1, 16], 1024)):
+                        ([1, 2, 4], 8), ([8, 1, 16], 1024), ([-1, -1, -1], 0), ([-1, 2, -1], 16)):
         lib.set_tuning(levels=[3, 4, 5], slabs=slabs, persist_blocks=grid)
         y1 = lib.apply_scaled(xt, kt)
         torch.cuda.synchronize()

@@ -139,3 +139,39 @@ def test_cube24_level7_block_jacobi_beats_plain_cg():
     print(f"  block Jacobi {i_bj}\n  none {i_no}", flush=True)
     assert i_bj["status"] == "HHG_OK" and i_no["status"] == "HHG_OK"
     assert i_bj["rel_residual"] <= 1e-6 and i_bj["iterations"] < i_no["iterations"]
+
+
+@pytest.mark.parametrize("solver", ["cg64", "ir32", "fcg64"])
+def test_eager_solve_matches_graph(solver, monkeypatch):
+    """HHG_NO_GRAPH=1 runs every iteration block by direct launches instead
+    of replaying the captured graph: the same kernels in the same order, so
+    the same iterates bit for bit."""
+    lib, orc, s2n = make(W.kuhn6(), 4, EFORM)
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(2, 0), 16, 1.0)
+    b = W.uniform_vector(3 * orc.n_nodes, W.rng_for(2, 17)).reshape(-1, 3)
+    b[orc.dirichlet] = 0
+    x1, i1, _, _, rel1 = solve_case(lib, orc, s2n, EFORM, k, b, solver=solver, check_every=8)
+    monkeypatch.setenv("HHG_NO_GRAPH", "1")
+    x2, i2, _, _, rel2 = solve_case(lib, orc, s2n, EFORM, k, b, solver=solver, check_every=8)
+    monkeypatch.delenv("HHG_NO_GRAPH")
+    assert i1["status"] == i2["status"] == "HHG_OK"
+    assert np.array_equal(x1, x2) and i1["iterations"] == i2["iterations"]
+    assert rel1 <= 1e-8 and rel2 <= 1e-8
+
+
+def test_iterations_to_tolerance_within_block():
+    """Iterations run in blocks of check_every; the count reported is the
+    first iteration whose recursive residual met the tolerance, the same as
+    with a check after every iteration, and iterations_run covers whole
+    blocks."""
+    lib, orc, s2n = make(W.kuhn6(), 4, EFORM)
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(2, 0), 16, 1.0)
+    b = W.uniform_vector(3 * orc.n_nodes, W.rng_for(2, 18)).reshape(-1, 3)
+    b[orc.dirichlet] = 0
+    _, i1, *_ = solve_case(lib, orc, s2n, EFORM, k, b, check_every=1)
+    _, i16, *_ = solve_case(lib, orc, s2n, EFORM, k, b, check_every=16)
+    assert i1["status"] == i16["status"] == "HHG_OK"
+    assert i1["iterations"] == i1["iterations_run"]
+    assert i16["iterations"] == i1["iterations"]
+    assert i16["iterations_run"] % 16 == 0
+    assert i16["iterations"] <= i16["iterations_run"] < i16["iterations"] + 16
