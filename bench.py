@@ -34,11 +34,25 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 64 FP64 FMA lanes per clock x 2
 FP32_VECTOR_PEAK_TFLOPS = 157.3    # published; twice the FP64 rate only with packed FP32
 BYTES_PER_INTERIOR_NODE = {"f64": 56.0, "f32": 28.0}   # x (3) + k (1) read, y (3) written
-# Operations per updated node of the physically scaled 3-D vector operator:
-# the paper's count for the residual (Table tab:operations: 855 = 242 + 123 +
-# 135 additions, 220 + 135 multiplications), less the 3 subtractions of the
-# right-hand side that an apply does not perform.
-FLOP_PER_INTERIOR_NODE = 852.0
+# Operations per updated node: the interior kernel's own count, 311 fused
+# multiply-adds (2 each), 150 additions and 14 multiplications of the ring
+# form with opposite directions sharing the reference stencil; and the
+# paper's count for the same update (Table tab:operations: 855 = 242 + 123 +
+# 135 additions, 220 + 135 multiplications for the residual, less the 3
+# subtractions of the right-hand side an apply does not perform), reported
+# beside it as the paper-equivalent rate.
+FLOP_PER_INTERIOR_NODE = 786.0
+PAPER_FLOP_PER_INTERIOR_NODE = 852.0
+# The paper's apply benchmark (Sec. 5.1.1, Fig. performancebars): FP64
+# residual updates of 3 DoF on a SuperMUC-NG node (2 x Xeon Platinum 8174,
+# 48 cores, 3.1 GHz nominal), 48 ranks x 3 level-7 macros (the paper's L = 5)
+PAPER_APPLY = dict(hardware="SuperMUC-NG node: 2 x Intel Xeon Platinum 8174, 48 cores, 3.1 GHz",
+                   ns_per_update=dict(physical_scaling=222, nodal_integration=393, stored_stencils=275),
+                   MDoF_s_node=dict(physical_scaling=round(48 * 3 / 222e-9 / 1e6, 1),
+                                    nodal_integration=round(48 * 3 / 393e-9 / 1e6, 1),
+                                    stored_stencils=round(48 * 3 / 275e-9 / 1e6, 1)),
+                   source="Sec. 5.1.1, Fig. performancebars (time per update); node rates derived "
+                          "as 48 ranks x 3 DoF per update time")
 N_SETS = 5
 
 
@@ -304,6 +318,24 @@ def batch_workload(dev, launches=20, count=10):
     ms_per_apply = e0.elapsed_time(e1) / (launches * count)
     mesh.graph_destroy(gid)
     dofs = 3 * mesh.n_unknown
+    # the graph replays one input set (x, k, y), which fits the 256 MB
+    # Infinity Cache; direct applies rotating over enough sets to exceed it
+    # twice over give the rate with inputs streamed from HBM
+    set_bytes = 2 * x32.numel() * 4 + k32.numel() * 4
+    n_sets = max(3, -(-512 * 2**20 // set_bytes))
+    rot = [(torch.from_numpy(W.uniform_vector(3 * mesh.n_nodes, W.rng_for(4, 10 + s)).reshape(3, -1))
+            .to(dev, torch.float32), k32.clone(), torch.empty_like(x32)) for s in range(n_sets)]
+    for s in range(2 * n_sets):
+        mesh.apply_scaled(*rot[s % n_sets], stream=stream)
+    torch.cuda.synchronize()
+    n_rot = n_sets * max(1, (10 * launches) // n_sets)
+    e0.record(stream)
+    for s in range(n_rot):
+        mesh.apply_scaled(*rot[s % n_sets], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_rot = e0.elapsed_time(e1) / n_rot
+    rot = None
     # accuracy: FP32 result against the FP64 apply, per problem
     y64 = mesh.apply_scaled(x32.double(), k32.double())
     torch.cuda.synchronize()
@@ -318,6 +350,11 @@ def batch_workload(dev, launches=20, count=10):
     return dict(problems=256, slots=mesh.n_nodes, unknown_dofs=dofs, dtype="f32",
                 applies_per_graph=count, ms_per_apply=round(ms_per_apply, 5),
                 MDoF_s=round(dofs / (ms_per_apply * 1e-3) / 1e6, 1),
+                MDoF_s_note="graph of applies on one input set (Infinity-Cache resident)",
+                ms_per_apply_hbm=round(ms_rot, 5),
+                MDoF_s_hbm=round(dofs / (ms_rot * 1e-3) / 1e6, 1),
+                MDoF_s_hbm_note=f"direct applies rotating over {n_sets} input sets of "
+                                f"{set_bytes / 1e6:.0f} MB (HBM resident)",
                 interior_GBs=round(28.0 * mesh.n_unknown / (rep["ms_total"] * 1e-3) / 1e9, 1),
                 persist_blocks=rep["persist_blocks"], tuning_candidates=rep["candidates"],
                 per_level=per_level,
@@ -432,7 +469,7 @@ def main():
     achieved = alg_bytes / (avg_int_ms * 1e-3) / 1e9
     rec = traffic_record() if args.level == 7 else None
     traffic = rec["traffic_bytes_per_launch"] if rec else None
-    # 852 FLOP per 56 B is 15.2 FLOP/B, above the FP64 ridge of 78.6 TF / 8 TB/s
+    # 786 FLOP per 56 B is 14.0 FLOP/B, above the FP64 ridge of 78.6 TF / 8 TB/s
     # = 9.8 FLOP/B: the apply is bound by FP64 vector arithmetic on this chip
     flops = FLOP_PER_INTERIOR_NODE * interior_rows
     tflops = flops / (avg_int_ms * 1e-3) / 1e12
@@ -445,6 +482,9 @@ def main():
                     profiled_loop_ms_per_step=round(prof_ms / args.steps, 5),
                     flop_per_launch=int(flops), units_per_launch=interior_rows,
                     flop_per_unit=FLOP_PER_INTERIOR_NODE,
+                    paper_flop_per_unit=PAPER_FLOP_PER_INTERIOR_NODE,
+                    paper_equivalent_tflops=round(PAPER_FLOP_PER_INTERIOR_NODE * interior_rows /
+                                                  (avg_int_ms * 1e-3) / 1e12, 2),
                     hbm=dict(achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_launch=int(alg_bytes),
                              bytes_per_unit=56))
@@ -569,6 +609,7 @@ def main():
                    "buffer_sets": N_SETS},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper": PAPER_APPLY,
         "kernels": kernels,
     }
     if extra:
