@@ -213,6 +213,18 @@ typedef struct {
 int hhg_preconditioner(hhg_handle h, int32_t precond, int32_t method, const double *k, double *P,
                        void *stream);
 
+/* The same blocks without allocating: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, results and errors as
+ * hhg_preconditioner.  The learned blocks use a static scratch array of
+ * 64 MiB on each device (held until the process ends; 68 bytes per slot,
+ * so at most 986,895 slots: larger meshes get HHG_EINVAL).  The handle must
+ * have made a device call already (its first one uploads its tables);
+ * otherwise HHG_EINVAL.  Calls that overlap on one device share the scratch
+ * and race: serialize them.  Synchronizes `stream`.                        */
+int hhg_preconditioner_noalloc(hhg_handle h, int32_t precond, int32_t method, const double *k,
+                               double *P, void *stream);
+
 /* Device workspace needed by hhg_cg_solve for these options (bytes).      */
 int hhg_workspace_bytes(hhg_handle h, const hhg_solve_opts *o, size_t *bytes);
 

@@ -141,6 +141,7 @@ SIGNATURES = {
                       ctypes.c_int),
     "hhg_set_learned_model": ([_VP, _VP], ctypes.c_int),
     "hhg_preconditioner": ([_VP, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "hhg_preconditioner_noalloc": ([_VP, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
     "hhg_mg_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(OpDesc), _I32, ctypes.POINTER(_VP)],
                       ctypes.c_int),
     "hhg_mg_destroy": ([_VP], ctypes.c_int),

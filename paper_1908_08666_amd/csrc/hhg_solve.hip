@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hhg_ctx.h"
@@ -756,6 +757,85 @@ int hhg_workspace_bytes(hhg_handle h, const hhg_solve_opts *o, size_t *bytes) {
   if (o->solver != HHG_CG_F64 && o->solver != HHG_IR_F32 && o->solver != HHG_FCG_F64)
     return hhg::fail(HHG_EINVAL, "unknown solver");
   *bytes = hhg::workspace_bytes(h, o->solver, o->precond);
+  return HHG_OK;
+}
+
+}  // extern "C"
+
+namespace hhg {
+namespace {
+// Scratch of hhg_preconditioner_noalloc: one static array on every device
+// the library runs on, held until the process ends.  Its device address is
+// looked up once per device (with that device current) and used for every
+// kernel argument; the array's name is a host-side stand-in.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_addr[MAX_DEVICES] = {};
+
+int scratch_ptr(void **out) {
+  int dev = 0;
+  HHG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(HHG_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    scratch_addr[dev] = p;
+  }
+  *out = scratch_addr[dev];
+  return HHG_OK;
+}
+
+// learned blocks: BF16 features [N][16] then FP32 network outputs [N][9]
+size_t learned_scratch_bytes(int64_t N, size_t *feat_bytes) {
+  const size_t fb = ((16 * (size_t)N * 2 + 255) / 256) * 256;
+  if (feat_bytes) *feat_bytes = fb;
+  return fb + 9 * (size_t)N * 4;
+}
+}  // namespace
+}  // namespace hhg
+
+extern "C" {
+
+int hhg_preconditioner_noalloc(hhg_handle h, int32_t precond, int32_t method, const double *k,
+                               double *P, void *stream) {
+  using namespace hhg;
+  if (!h || !k || !P) return fail(HHG_EINVAL, "null argument");
+  if (((uintptr_t)k | (uintptr_t)P) & 7) return fail(HHG_EINVAL, "misaligned pointer");
+  if (precond != HHG_PRECOND_NONE && precond != HHG_PRECOND_BLOCK_JACOBI &&
+      precond != HHG_PRECOND_LEARNED)
+    return fail(HHG_EINVAL, "unknown preconditioner");
+  if (method != HHG_METHOD_SCALED && method != HHG_METHOD_ONTHEFLY)
+    return fail(HHG_EINVAL, "unknown operator method");
+  if (precond == HHG_PRECOND_LEARNED && !h->model)
+    return fail(HHG_EINVAL, "learned preconditioner requested but no model is attached");
+  const int64_t N = h->n_nodes;
+  size_t fb = 0;
+  if (precond == HHG_PRECOND_LEARNED && learned_scratch_bytes(N, &fb) > NOALLOC_SCRATCH_BYTES)
+    return fail(HHG_EINVAL, "learned blocks of " + std::to_string(N) + " slots need " +
+                                std::to_string(learned_scratch_bytes(N, nullptr)) +
+                                " scratch bytes, more than the static 64 MiB");
+  // the handle's tables are uploaded by its first device call, which
+  // allocates: this entry point only runs on a handle that had one
+  if (!h->on_device)
+    return fail(HHG_EINVAL, "handle not yet on a device: call any device entry point on it first");
+  int rc = ensure_device(h);   // on a device already: checks the current device only
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  void *s = nullptr;
+  if (precond == HHG_PRECOND_LEARNED && (rc = scratch_ptr(&s))) return rc;
+  if ((rc = diag_blocks(h, k, method, P, st))) return rc;
+  hipLaunchKernelGGL(k_invert, grid_for(N), dim3(256), 0, st, P, h->d_flags, N,
+                     precond == HHG_PRECOND_NONE ? 1 : 0);
+  HHG_HIP(hipGetLastError());
+  if (precond == HHG_PRECOND_LEARNED &&
+      (rc = learned_precond(h, k, P, static_cast<uint16_t *>(s),
+                            reinterpret_cast<float *>(static_cast<char *>(s) + fb), st)))
+    return rc;
+  HHG_HIP(hipStreamSynchronize(st));
   return HHG_OK;
 }
 

@@ -115,16 +115,21 @@ def attach(mesh: Mesh, net: SmootherNet | None):
     mesh._learned = net
 
 
-def preconditioner(mesh: Mesh, k, precond="learned", method="scaled", stream=None):
-    """Preconditioner blocks [6, n_nodes] (xx yy zz xy xz yz) a solve would use."""
+def preconditioner(mesh: Mesh, k, precond="learned", method="scaled", stream=None, P=None,
+                   noalloc=False):
+    """Preconditioner blocks [6, n_nodes] (xx yy zz xy xz yz) a solve would
+    use; noalloc=True calls the allocation-free entry point (P may then be
+    passed in, so that nothing is allocated on this path either)."""
     import torch
     N = mesh.n_nodes
-    P = torch.empty((6, N), dtype=torch.float64, device=k.device)
+    if P is None:
+        P = torch.empty((6, N), dtype=torch.float64, device=k.device)
     pc = {"none": L.HHG_PRECOND_NONE, "block_jacobi": L.HHG_PRECOND_BLOCK_JACOBI,
           "learned": L.HHG_PRECOND_LEARNED}[precond]
     m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
-    L.check(mesh._lib.hhg_preconditioner(mesh._h, pc, m, _dev_ptr(k, (N,), torch.float64),
-                                         ctypes.c_void_p(P.data_ptr()), _stream_ptr(stream)))
+    fn = mesh._lib.hhg_preconditioner_noalloc if noalloc else mesh._lib.hhg_preconditioner
+    L.check(fn(mesh._h, pc, m, _dev_ptr(k, (N,), torch.float64), _dev_ptr(P, (6, N), torch.float64),
+               _stream_ptr(stream)))
     return P
 
 
