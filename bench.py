@@ -574,6 +574,8 @@ def main():
             "unphysical": dict(corr="none", op_method="scaled", iface="rowwise", method="cycle"),
             "physical_symmetric_rule": dict(corr="physical", op_method="scaled", iface="symmetric",
                                             method="cg"),
+            "physical_zerosum_rule": dict(corr="physical", op_method="scaled", iface="zerosum",
+                                          method="cg"),
             "physical_f32_cycles": dict(corr="physical", op_method="scaled", iface="rowwise",
                                         method="cycle", precision="f32"),
         }

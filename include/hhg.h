@@ -70,7 +70,7 @@ enum hhg_coupling { HHG_CONFORMING = 0, HHG_INDEPENDENT = 1 };
 enum hhg_dirichlet { HHG_DIRICHLET_OUTER = 0, HHG_DIRICHLET_NONE = 1 };
 enum hhg_corr { HHG_CORR_PHYSICAL = 0, HHG_CORR_NONE = 1 };
 enum hhg_khat { HHG_KHAT_PATCH = 0, HHG_KHAT_EDGE = 1 };
-enum hhg_iface { HHG_IFACE_SYMMETRIC = 0, HHG_IFACE_ROWWISE = 1 };
+enum hhg_iface { HHG_IFACE_SYMMETRIC = 0, HHG_IFACE_ROWWISE = 1, HHG_IFACE_ZEROSUM = 2 };
 enum hhg_method { HHG_METHOD_SCALED = 0, HHG_METHOD_ONTHEFLY = 1 };
 
 /* Macro mesh (Sec. 2: macro triangulation T_H refined uniformly).
@@ -101,7 +101,12 @@ typedef struct {
  *          HHG_IFACE_SYMMETRIC: nodal-integration entries where both nodes lie
  *          on the macro boundary (and on the diagonal), scaled entries
  *          towards macro-interior nodes -- a symmetric matrix;
- *          HHG_IFACE_ROWWISE: the full nodal-integration row.                 */
+ *          HHG_IFACE_ROWWISE: the full nodal-integration row;
+ *          HHG_IFACE_ZEROSUM (not in the paper): the entries of the symmetric
+ *          rule off the diagonal and a centre block of minus the sum of the
+ *          row's other blocks, as on macro-interior rows; still symmetric,
+ *          and translations stay in the kernel of the interface rows.
+ *          The on-the-fly method always uses the nodal row.                   */
 typedef struct {
   double mu0, lam0;
   double mu1, lam1;

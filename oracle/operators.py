@@ -30,7 +30,12 @@ Methods
 Rows of nodes on a macro boundary follow Sec. 2.2: ``iface='symmetric'`` uses
 nodal entries when both x_i and x_j lie on dT of the macro and the scaled entry
 otherwise (diagonal nodal); ``iface='rowwise'`` uses the nodal row for every
-node on a macro boundary.
+node on a macro boundary; ``iface='zerosum'`` takes the off-diagonal entries
+of the symmetric rule and sets the centre of every row to minus the sum of
+the others, as the Lemma does for macro-interior rows (not in the paper: the
+interface rows then keep translations in their kernel, and since the
+off-diagonal entries are those of a symmetric matrix and their block row sums
+are symmetric 3x3 blocks, the matrix stays symmetric).
 
 Parity: pinned by tests against what the paper fixes (equal to nodal
 integration for constant and for affine k on macro-interior rows, unphysical
@@ -42,7 +47,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .forms import form_tensor, sym_part, antisym_part
+from .forms import form_tensor, sym_part, antisym_part, p1_gradients
 from .mesh import MacroMesh
 
 
@@ -162,7 +167,7 @@ def scaled_matrix(mesh: MacroMesh, k, op, rows=None, corr="physical",
         raise ValueError(corr)
     if khat not in ("patch", "edge"):
         raise ValueError(khat)
-    if iface not in ("symmetric", "rowwise"):
+    if iface not in ("symmetric", "rowwise", "zerosum"):
         raise ValueError(iface)
     k = np.asarray(k, dtype=np.float64)
     rows_mask = _rows_mask(mesh, rows)
@@ -250,23 +255,27 @@ def scaled_matrix(mesh: MacroMesh, k, op, rows=None, corr="physical",
 
         i_int = ~onb[ei]
         j_int = ~onb[ej]
-        use_scaled = i_int | ((iface == "symmetric") & j_int)
+        use_scaled = i_int | ((iface != "rowwise") & j_int)
         if np.any(use_scaled & ~complete):
             raise RuntimeError("scaled entry requested on an incomplete edge patch")
         value = np.where(use_scaled[:, None, None], scaled, nodal)
         _emit(value, gid[ei], gid[ej], R, C, V)
 
-        # centre entries
+        # centre entries: minus the sum of the row's other entries from this
+        # macro (macro-interior rows; every row under the zero-sum rule)
         diag = np.zeros((N, 3, 3))
-        rows_int = i_int
+        rows_int = i_int | (iface == "zerosum")
         np.add.at(diag, ei[rows_int], -value[rows_int])
-        # nodes on dT: nodal diagonal from this macro's elements
+        # nodes on dT (symmetric and row-wise rules): nodal diagonal from this
+        # macro's elements
         dsel = []
         for a in range(4):
             il = tets[:, a]
             keep = onb[il]
             if local_rows is not None:
                 keep &= local_rows[il]
+            if iface == "zerosum":
+                keep = np.zeros_like(keep)
             dsel.append((il[keep], a0[keep, a, a] + kbar[keep, None, None] * a1[keep, a, a]))
         for il, blk in dsel:
             np.add.at(diag, il, blk)
@@ -284,6 +293,23 @@ def scaled_matrix(mesh: MacroMesh, k, op, rows=None, corr="physical",
                               A0=A0sum[sel_int], count=cnt[sel_int]))
     A = _to_csr(mesh, R, C, V)
     return (A, parts) if return_parts else A
+
+
+def mass_matrix(mesh: MacroMesh) -> sp.csr_matrix:
+    """Scalar P1 mass matrix (n_nodes x n_nodes): the element integral of
+    phi_a phi_b is |t| (1 + delta_ab) / 20."""
+    R, C, V = [], [], []
+    for m in range(mesh.n_macro):
+        tets = mesh.local_tets[m]
+        _, vol = p1_gradients(mesh.local_xyz[m][tets])
+        g = mesh.gid[m][tets]
+        for a in range(4):
+            for b in range(4):
+                R.append(g[:, a])
+                C.append(g[:, b])
+                V.append(vol * ((2.0 if a == b else 1.0) / 20.0))
+    n = mesh.n_nodes
+    return sp.csr_matrix((np.concatenate(V), (np.concatenate(R), np.concatenate(C))), shape=(n, n))
 
 
 def operator_matrix(mesh, k, op, method="scaled", **kw):

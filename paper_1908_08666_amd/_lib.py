@@ -13,7 +13,7 @@ HHG_CONFORMING, HHG_INDEPENDENT = 0, 1
 HHG_DIRICHLET_OUTER, HHG_DIRICHLET_NONE = 0, 1
 HHG_CORR_PHYSICAL, HHG_CORR_NONE = 0, 1
 HHG_KHAT_PATCH, HHG_KHAT_EDGE = 0, 1
-HHG_IFACE_SYMMETRIC, HHG_IFACE_ROWWISE = 0, 1
+HHG_IFACE_SYMMETRIC, HHG_IFACE_ROWWISE, HHG_IFACE_ZEROSUM = 0, 1, 2
 HHG_METHOD_SCALED, HHG_METHOD_ONTHEFLY = 0, 1
 HHG_K_INTERIOR_SCALED, HHG_K_INTERIOR_ONTHEFLY, HHG_K_BOUNDARY_ROWS, HHG_K_GROUP_SUM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "interior_scaled", 1: "interior_onthefly", 2: "boundary_rows", 3: "group_sum",

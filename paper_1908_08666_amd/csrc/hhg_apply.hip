@@ -60,7 +60,10 @@ __device__ __forceinline__ void boundary_gather(const MacroInfo &mi, int i, int 
 // One macro-boundary row of macro m at (i, j, k) from its gathered
 // neighbour data: the macro's partial row (or, for a node without copies in
 // other macros and RESID, f minus the row) is written to the node's slot.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+// ZS (zero-sum centre): every neighbour value enters as x_j - x_i and the
+// nodal centre term is dropped, so the centre block becomes minus the sum of
+// the row's other blocks.
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS>
 __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilConst<T> &sc,
                                              const ElemConst<T> &ec, int i, int j, int k,
                                              const BoundaryNbr<T> &b,
@@ -83,11 +86,15 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
     for (int c = 0; c < 4; ++c) {
       T d0, d1, d2;
       if (c == 0) {
+        if (ZS) continue;
         d0 = ci0; d1 = ci1; d2 = ci2;
       } else {
         const int v = TET_V[t][c - 1];
         if (!ROWWISE && !onb[v]) continue;   // scaled entry handled below
         d0 = nx0[v]; d1 = nx1[v]; d2 = nx2[v];
+        if (ZS) {
+          d0 -= ci0; d1 -= ci1; d2 -= ci2;
+        }
       }
       const T *B1 = ec.b1[t][c];
       u0 = fma(B1[0], d0, fma(B1[1], d1, fma(B1[2], d2, u0)));
@@ -115,9 +122,11 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
       const T wr = DIR_NT[d] == 6 ? sc.w_ring6 : sc.w_ring4;
       const T kh = fma(sc.w_end, ck + nk[d], wr * ring);
       const T *S = sc.pr[d >> 1].shat;
-      const T z0v = kh * nx0[d], z1v = kh * nx1[d], z2v = kh * nx2[d];
+      const T e0 = ZS ? nx0[d] - ci0 : nx0[d], e1 = ZS ? nx1[d] - ci1 : nx1[d],
+              e2 = ZS ? nx2[d] - ci2 : nx2[d];
+      const T z0v = kh * e0, z1v = kh * e1, z2v = kh * e2;
       sym_mv_acc(S, z0v, z1v, z2v, y0, y1, y2);
-      if constexpr (A0) sym_mv_acc(sc.pr[d >> 1].a0, nx0[d], nx1[d], nx2[d], y0, y1, y2);
+      if constexpr (A0) sym_mv_acc(sc.pr[d >> 1].a0, e0, e1, e2, y0, y1, y2);
       if (CORR) {
         T w0 = T(0), w1 = T(0), w2 = T(0);
 #pragma unroll
@@ -127,7 +136,7 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
           w1 = fma(dk, sc.pr[d >> 1].cax[q][1], w1);
           w2 = fma(dk, sc.pr[d >> 1].cax[q][2], w2);
         }
-        cross_acc(w0, w1, w2, nx0[d], nx1[d], nx2[d], y0, y1, y2);
+        cross_acc(w0, w1, w2, e0, e1, e2, y0, y1, y2);
       }
     }
   }
@@ -197,7 +206,7 @@ constexpr int TILE_BYTES = (int)(2 * 4 * FT_P * sizeof(T));
 // HBM.  The rows of a block belong to one macro (bblk) and are ordered by the
 // boundary primitive they lie on, so that a wave rarely diverges; Dirichlet
 // slots (bit 30 in bijk) get their zero rows.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS>
 __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
                                             const MacroInfo *__restrict__ minfo,
                                             const StencilConst<T> *__restrict__ scs,
@@ -239,7 +248,7 @@ __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
   }
   const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(smem);
   const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(smem + sizeof(ElemConst<T>));
-  boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+  boundary_row<T, RESID, ROWWISE, CORR, A0, ZS>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
 }
 
 // Displacement (da, db, dl) in face coordinates of lattice direction d for
@@ -267,7 +276,7 @@ __host__ __device__ constexpr int face_dl(int d) {
 // layer inside the macro and those in front of the face outside it, so with
 // the face fixed at compile time every neighbour's role and LDS offset is a
 // constant and the row needs no branches.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, int FACE>
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS, int FACE>
 __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *smem,
                                           const MacroInfo *__restrict__ minfo,
                                           const StencilConst<T> *__restrict__ scs,
@@ -349,7 +358,7 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
     nb.ci1 = tile[0][1][pc];
     nb.ci2 = tile[0][2][pc];
     nb.ck = tile[0][3][pc];
-    boundary_row<T, RESID, ROWWISE, CORR, A0>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+    boundary_row<T, RESID, ROWWISE, CORR, A0, ZS>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
   }
 }
 
@@ -357,10 +366,11 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
 // computes the partial row of its macro; copies are summed afterwards.
 // ROWWISE: nodal integration for the whole row (also the on-the-fly method);
 // otherwise scaled entries towards macro-interior neighbours and nodal
-// entries towards macro-boundary neighbours and on the diagonal.  One launch
+// entries towards macro-boundary neighbours, with the nodal diagonal or (ZS)
+// the zero-sum centre.  One launch
 // covers all of them: the first nft blocks are face tiles, the rest blocks
 // of listed rows, so that the whole boundary is queued at once.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0>
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS>
 __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const FaceTile *__restrict__ tiles, int nft,
@@ -372,7 +382,7 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
     const FaceTile ft = tiles[blockIdx.x];
     switch (__builtin_amdgcn_readfirstlane(ft.face)) {
 #define HHG_FR(F)                                                                                 \
-  face_rows<T, RESID, ROWWISE, CORR, A0, F>(ft, smem, minfo, scs, ecs, flags, x, kc, f, y, nn); \
+  face_rows<T, RESID, ROWWISE, CORR, A0, ZS, F>(ft, smem, minfo, scs, ecs, flags, x, kc, f, y, nn); \
   break
       case 0: HHG_FR(0);
       case 1: HHG_FR(1);
@@ -381,8 +391,8 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
 #undef HHG_FR
     }
   } else
-    listed_rows<T, RESID, ROWWISE, CORR, A0>((int)blockIdx.x - nft, smem, minfo, scs, ecs, bijk,
-                                             bblk, flags, x, kc, f, y, nn);
+    listed_rows<T, RESID, ROWWISE, CORR, A0, ZS>((int)blockIdx.x - nft, smem, minfo, scs, ecs, bijk,
+                                                 bblk, flags, x, kc, f, y, nn);
 }
 
 // Sum of the partial rows of all copies of an interface node; the total (or
@@ -424,24 +434,28 @@ template <typename T, bool RESID>
 int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, T *y,
                     hipStream_t st) {
   const bool rowwise = method == METHOD_ONTHEFLY || h->op.iface == HHG_IFACE_ROWWISE;
+  const bool zs = !rowwise && h->op.iface == HHG_IFACE_ZEROSUM;
   const bool corr = h->op.corr == HHG_CORR_PHYSICAL;
   const int nft = (int)h->ftile.size();
   const int nblk = nft + (int)h->bblk.size();
   if (nblk > 0) {
     const dim3 grid((unsigned)nblk);
-#define HHG_LB(RW, CR, A0)                                                                       \
-  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR, A0>), grid, dim3(BOUNDARY_BLOCK), 0, st, \
-                     h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_ftile, nft, h->d_bijk,          \
+#define HHG_LB(RW, CR, A0, ZS)                                                                       \
+  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR, A0, ZS>), grid, dim3(BOUNDARY_BLOCK), 0, st, \
+                     h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_ftile, nft, h->d_bijk,              \
                      h->d_bblk, h->d_flags, x, k, f, y, h->n_nodes)
+#define HHG_LB2(CR, A0) \
+  if (zs) HHG_LB(false, CR, A0, true); else HHG_LB(false, CR, A0, false)
     ProfScope prof(h, HHG_K_BOUNDARY_ROWS, st);
     const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
     if (rowwise) {
-      if (a0) HHG_LB(true, false, true); else HHG_LB(true, false, false);
+      if (a0) HHG_LB(true, false, true, false); else HHG_LB(true, false, false, false);
     } else if (corr) {
-      if (a0) HHG_LB(false, true, true); else HHG_LB(false, true, false);
+      if (a0) { HHG_LB2(true, true); } else { HHG_LB2(true, false); }
     } else {
-      if (a0) HHG_LB(false, false, true); else HHG_LB(false, false, false);
+      if (a0) { HHG_LB2(false, true); } else { HHG_LB2(false, false); }
     }
+#undef HHG_LB2
 #undef HHG_LB
     HHG_HIP(hipGetLastError());
   }

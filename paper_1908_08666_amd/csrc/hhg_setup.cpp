@@ -834,7 +834,8 @@ int hhg_setup_macro(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_handle
     return fail(HHG_EINVAL, "unknown dirichlet mode");
   if ((op->corr != HHG_CORR_PHYSICAL && op->corr != HHG_CORR_NONE) ||
       (op->khat != HHG_KHAT_PATCH && op->khat != HHG_KHAT_EDGE) ||
-      (op->iface != HHG_IFACE_SYMMETRIC && op->iface != HHG_IFACE_ROWWISE))
+      (op->iface != HHG_IFACE_SYMMETRIC && op->iface != HHG_IFACE_ROWWISE &&
+       op->iface != HHG_IFACE_ZEROSUM))
     return fail(HHG_EINVAL, "unknown operator variant");
   if (!std::isfinite(op->mu0) || !std::isfinite(op->mu1) || !std::isfinite(op->lam0) ||
       !std::isfinite(op->lam1))

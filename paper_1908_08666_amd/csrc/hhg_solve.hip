@@ -279,8 +279,8 @@ __device__ __forceinline__ int zero_set_d(int i, int j, int k, int n) {
 __global__ __launch_bounds__(256) void k_diag(const MacroInfo *__restrict__ minfo,
                                               const StencilConst<double> *__restrict__ scs,
                                               const ElemConst<double> *__restrict__ ecs,
-                                              const double *__restrict__ kc, int method, int64_t N,
-                                              double *__restrict__ D) {
+                                              const double *__restrict__ kc, int method,
+                                              int zerosum, int64_t N, double *__restrict__ D) {
   const int m = blockIdx.y;
   const MacroInfo mi = minfo[m];
   const int n = mi.n;
@@ -309,7 +309,42 @@ __global__ __launch_bounds__(256) void k_diag(const MacroInfo *__restrict__ minf
     bool in[NDIR];
     for (int dd = 0; dd < NDIR; ++dd) nk[dd] = kat(dd, in[dd]);
     const double kc0 = K[ls];
-    if (z == 0 && method == HHG_METHOD_SCALED) {
+    if (z != 0 && zerosum && method == HHG_METHOD_SCALED) {
+      // zero-sum centre of an interface row: minus this macro's part of the
+      // row's other blocks, nodal towards macro-boundary neighbours and
+      // scaled towards macro-interior ones (the correction blocks are
+      // antisymmetric and drop out of the symmetric part kept here; the
+      // copies' partial centres sum to a symmetric block)
+      bool onb[NDIR];
+      for (int dd = 0; dd < NDIR; ++dd)
+        onb[dd] = in[dd] && zero_set_d(i + DIR_I[dd], j + DIR_J[dd], k + DIR_K[dd], n) != 0;
+      const ElemConst<double> &ec = ecs[m];
+      const int ix[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+      for (int t = 0; t < NTET; ++t) {
+        const int v1 = TET_V[t][0], v2 = TET_V[t][1], v3 = TET_V[t][2];
+        if (!(in[v1] && in[v2] && in[v3])) continue;
+        const double kb = 0.25 * (kc0 + nk[v1] + nk[v2] + nk[v3]);
+        for (int c = 1; c < 4; ++c) {
+          if (!onb[TET_V[t][c - 1]]) continue;
+          const double *B1 = ec.b1[t][c];
+          const double *B0 = ec.b0[t][c];
+          for (int q = 0; q < 6; ++q) {
+            const int a = 3 * ix[q][0] + ix[q][1], b = 3 * ix[q][1] + ix[q][0];
+            d[q] -= 0.5 * ((B0[a] + kb * B1[a]) + (B0[b] + kb * B1[b]));
+          }
+        }
+      }
+      const StencilConst<double> &sc = scs[m];
+      for (int dd = 0; dd < NDIR; ++dd) {
+        if (!in[dd] || onb[dd]) continue;
+        const int np = DIR_NT[dd] == 6 ? 3 : 2;
+        double ring = 0.0;
+        for (int q = 0; q < np; ++q) ring += nk[RING_V[dd][q]] + nk[RING_VM[dd][q]];
+        const double wr = DIR_NT[dd] == 6 ? sc.w_ring6 : sc.w_ring4;
+        const double kh = sc.w_end * (kc0 + nk[dd]) + wr * ring;
+        for (int q = 0; q < 6; ++q) d[q] -= kh * sc.pr[dd >> 1].shat[q] + sc.pr[dd >> 1].a0[q];
+      }
+    } else if (z == 0 && method == HHG_METHOD_SCALED) {
       const StencilConst<double> &sc = scs[m];
       for (int dd = 0; dd < NDIR; ++dd) {
         const int np = DIR_NT[dd] == 6 ? 3 : 2;
@@ -389,7 +424,7 @@ int diag_blocks(hhg_ctx *h, const double *k, int method, double *D, hipStream_t 
   for (auto &mi : h->minfo) maxn = std::max(maxn, (int)macro_nodes(mi.n));
   const int64_t N = h->n_nodes;
   hipLaunchKernelGGL(k_diag, dim3((maxn + 255) / 256, h->n_macro), dim3(256), 0, st, h->d_minfo,
-                     h->d_sc64, h->d_ec64, k, method, N, D);
+                     h->d_sc64, h->d_ec64, k, method, h->op.iface == HHG_IFACE_ZEROSUM ? 1 : 0, N, D);
   if (h->n_grp > 0)
     hipLaunchKernelGGL(k_group_sum6, dim3((unsigned)((6 * h->n_grp + 255) / 256)), dim3(256), 0, st,
                        h->d_grp_ptr, h->d_grp_slot, h->n_grp, D, N);

@@ -56,7 +56,8 @@ def _descriptors(verts, levels, mu0, lam0, mu1, lam1, coupling, dirichlet, corr,
     od = L.OpDesc(mu0, lam0, mu1, lam1,
                   {"physical": L.HHG_CORR_PHYSICAL, "none": L.HHG_CORR_NONE}[corr],
                   {"patch": L.HHG_KHAT_PATCH, "edge": L.HHG_KHAT_EDGE}[khat],
-                  {"symmetric": L.HHG_IFACE_SYMMETRIC, "rowwise": L.HHG_IFACE_ROWWISE}[iface])
+                  {"symmetric": L.HHG_IFACE_SYMMETRIC, "rowwise": L.HHG_IFACE_ROWWISE,
+                   "zerosum": L.HHG_IFACE_ZEROSUM}[iface])
     return md, od, (verts, lv)
 
 

@@ -83,7 +83,7 @@ def test_unit_tet_level4_ten_inputs(dtype, method):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("iface", ["symmetric", "rowwise"])
+@pytest.mark.parametrize("iface", ["symmetric", "rowwise", "zerosum"])
 def test_kuhn6_multi_macro(dtype, iface):
     """Six conforming macros (cube), interface rows summed over copies."""
     lib, orc, s2n = setup_case(W.kuhn6(), 3, EFORM, iface=iface)
@@ -101,6 +101,15 @@ def test_cube24_eps_operator(dtype):
     x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(3, 1)).reshape(-1, 3)
     check(lib, orc, s2n, k, EPS, x, dtype, "scaled")
     check(lib, orc, s2n, k, EPS, x, dtype, "onthefly")
+
+
+def test_cube24_zerosum_rule():
+    """Zero-sum interface centre on 24 macros (edges shared by up to six
+    macros, the cube centre by all 24), with an unscaled part of the form."""
+    lib, orc, s2n = setup_case(W.cube24(), 3, LAME1, iface="zerosum")
+    k = W.exp_fourier_coefficient(orc.xyz, W.rng_for(3, 2), 8, 1.5)
+    x = W.uniform_vector(3 * orc.n_nodes, W.rng_for(3, 3)).reshape(-1, 3)
+    check(lib, orc, s2n, k, LAME1, x, torch.float64, "scaled", iface="zerosum")
 
 
 @pytest.mark.parametrize("op,dtype", [("lame1", torch.float64), ("lame1", torch.float32),

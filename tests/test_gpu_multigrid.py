@@ -191,12 +191,15 @@ def test_cycles_need_the_workspace_of_the_coefficient_setup():
 
 @pytest.mark.parametrize("method,iface,corr", [("onthefly", "symmetric", "physical"),
                                                ("scaled", "rowwise", "physical"),
-                                               ("scaled", "symmetric", "none")])
+                                               ("scaled", "symmetric", "none"),
+                                               ("scaled", "zerosum", "physical")])
 def test_vcycle_variants_match_oracle(method, iface, corr):
     """V-cycles for the nodal-integration operator, the row-wise interface
-    rule (a non-symmetric matrix: the coarse solve pivots) and the
-    unphysical scaling against the oracle's cycle of the same operator; for
-    the row-wise rule also the V-cycle iteration against the direct solve."""
+    rule (a non-symmetric matrix: the coarse solve pivots), the unphysical
+    scaling and the zero-sum interface centre (whose smoother blocks are the
+    zero-sum centres) against the oracle's cycle of the same operator; for
+    the row-wise rule also the V-cycle iteration, for the zero-sum rule
+    V-cycle CG, against the direct solve."""
     mg, orcs, s2n, V = hierarchy("kuhn6", 4, iface=iface, corr=corr)
     f = orcs[-1]
     k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 5), 16, 1.0)
@@ -210,8 +213,8 @@ def test_vcycle_variants_match_oracle(method, iface, corr):
     err = rel_err(z[f.unknown], ref[f.unknown])
     print(f"  {method} {iface} {corr}: V-cycle rel err {err:.2e}", flush=True)
     assert err <= 1e-10
-    if iface == "rowwise":
-        x_d, info = mg.solve(r_d, rtol=1e-11, maxit=80, method="cycle")
+    if iface in ("rowwise", "zerosum"):
+        x_d, info = mg.solve(r_d, rtol=1e-11, maxit=80, method="cycle" if iface == "rowwise" else "cg")
         assert info["status"] == "HHG_OK"
         x = gather_consistent(x_d.cpu().numpy(), s2n[-1], f.n_nodes)
         xs = node_vec(spla.spsolve(H.A[-1].tocsc(), dof_vec(r, f)), f)

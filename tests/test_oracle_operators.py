@@ -229,3 +229,89 @@ def test_apply_handles_dirichlet():
     rows = u[::5]
     ys = O.apply(mesh, k, MIXED, x, rows=rows)
     np.testing.assert_allclose(ys[rows], y[rows], rtol=1e-13, atol=1e-15)
+
+
+def test_zerosum_rule(mesh):
+    """Zero-sum interface rule: the symmetric rule's off-diagonal entries, a
+    centre of minus the row's other entries on every row.  Symmetric,
+    translations in the kernel of every row (interface rows included), equal
+    to the symmetric rule on macro-interior rows and to nodal integration for
+    constant k."""
+    k = W.sine_coefficient(mesh.xyz) + 0.3 * np.cos(7 * mesh.xyz[:, 0])
+    Az = O.scaled_matrix(mesh, k, EFORM, iface="zerosum").tocsr()
+    As = O.scaled_matrix(mesh, k, EFORM).tocsr()
+    scale = abs(As).max()
+    assert abs(Az - Az.T).max() < 1e-14 * scale
+    for c in range(3):
+        t = np.zeros((mesh.n_nodes, 3))
+        t[:, c] = 1.0
+        assert np.abs(Az @ t.ravel()).max() < 1e-13 * scale
+    irows = _interior_dofs(mesh)
+    assert abs(Az[irows] - As[irows]).max() < 1e-14 * scale
+    # off the 3x3 diagonal blocks the two rules agree entry by entry
+    n = mesh.n_nodes
+    blockdiag = sp.kron(sp.identity(n), np.ones((3, 3))).tocsr()
+    D = (Az - As).tocsr()
+    assert abs(D - D.multiply(blockdiag)).max() < 1e-15 * scale
+    if mesh.interface.any():
+        assert abs(D).max() > 1e-6 * scale        # the centre does change
+    kc = np.full(mesh.n_nodes, 1.7)
+    assert _rel(O.scaled_matrix(mesh, kc, EFORM, iface="zerosum"), O.nodal_matrix(mesh, kc, EFORM)) < 1e-13
+
+
+def test_zerosum_spd_after_dirichlet():
+    mesh = MacroMesh(W.kuhn6(), 2)
+    k = np.exp(W.fourier_field(mesh.xyz, W.rng_for(2), 16, 1.0))
+    Az = O.reduce_dirichlet(mesh, O.scaled_matrix(mesh, k, EFORM, iface="zerosum")).toarray()
+    assert np.abs(Az - Az.T).max() < 1e-14 * np.abs(Az).max()
+    assert np.linalg.eigvalsh(Az).min() > 0
+
+
+def test_mass_matrix_closed_form():
+    """P1 mass: total |Omega|, symmetric, and on the Kuhn lattice an interior
+    row is h^3 (2/5 at the node, 1/20 towards the 8 neighbours along the
+    six-element edges, 1/30 towards the 6 along the four-element edges)."""
+    L = 3
+    mesh = MacroMesh(W.kuhn6(), L)
+    Mm = O.mass_matrix(mesh)
+    assert abs(Mm.sum() - 1.0) < 1e-13
+    assert abs(Mm - Mm.T).max() < 1e-17
+    h3 = 1.0 / 8 ** L
+    i = int(np.argmin(np.linalg.norm(mesh.xyz - 0.5, axis=1)))
+    row = Mm[i].toarray().ravel()
+    nb = np.flatnonzero(row)
+    vals = np.sort(row[nb] / h3)
+    assert np.allclose(vals, np.sort([0.4] + [1 / 20] * 8 + [1 / 30] * 6), rtol=1e-12, atol=0)
+
+
+def _elastostatics_error(level, iface, m=8):
+    """Discrete L2 nodal error of the direct solution of the elastostatics
+    problem of Sec. 5.1.2 (E = cos(m pi xyz) + 2, manufactured u*) on the
+    6-macro cube: load M I_h f, Dirichlet data u*."""
+    import scipy.sparse.linalg as spla
+    mesh = MacroMesh(W.kuhn6(), level)
+    x = mesh.xyz
+    k = W.elastostatics_modulus(x, m)
+    us = W.elastostatics_solution(x)
+    b = (O.mass_matrix(mesh) @ W.elastostatics_force(x, m)).ravel()
+    A = O.scaled_matrix(mesh, k, EFORM, iface=iface).tocsr()
+    unk = np.zeros(mesh.n_nodes, bool)
+    unk[mesh.unknown] = True
+    du = (3 * np.flatnonzero(unk)[:, None] + np.arange(3)).ravel()
+    db = (3 * np.flatnonzero(~unk)[:, None] + np.arange(3)).ravel()
+    g = us.ravel()
+    Arows = A[du]
+    w = spla.spsolve(Arows[:, du].tocsc(), b[du] - Arows[:, db] @ g[db])
+    return np.sqrt(np.sum((w - g[du]) ** 2) / 8 ** level)
+
+
+def test_zerosum_restores_second_order():
+    """With the nodal centre on interface rows (the paper's symmetric rule)
+    the elastostatics error for m = 8 falls at first order or below; the
+    zero-sum centre brings back the second order that physical scaling
+    reaches with the row-wise rule (Sec. 5.1.2)."""
+    e = {r: [_elastostatics_error(L, r) for L in (3, 4)] for r in ("symmetric", "zerosum", "rowwise")}
+    eoc = {r: np.log2(v[0] / v[1]) for r, v in e.items()}
+    assert eoc["zerosum"] > 1.8 and eoc["rowwise"] > 1.8
+    assert eoc["symmetric"] < 1.0
+    assert abs(e["zerosum"][1] / e["rowwise"][1] - 1) < 0.1
