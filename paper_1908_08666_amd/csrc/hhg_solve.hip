@@ -87,11 +87,11 @@ __global__ __launch_bounds__(RED_TPB) void k_dot2(const T *__restrict__ a, const
   }
 }
 
-// x += alpha p, r -= alpha q, z = P r; partial sums of (r, z) and (r, r),
-// and for the flexible variant (z, q)
+// r -= alpha q, z = P r; partial sums of (r, z) and (r, r), and for the
+// flexible variant (z, q).  The x update waits for k_pupdate, which reads p
+// anyway, so x and p stream through HBM once per iteration.
 template <typename T, bool FLEX>
-__global__ __launch_bounds__(RED_TPB) void k_update(T *__restrict__ x, const T *__restrict__ p,
-                                                    T *__restrict__ r, const T *__restrict__ q,
+__global__ __launch_bounds__(RED_TPB) void k_update(T *__restrict__ r, const T *__restrict__ q,
                                                     const T *__restrict__ P, T *__restrict__ z,
                                                     const uint8_t *__restrict__ fl, int64_t N,
                                                     const CGState *__restrict__ st,
@@ -104,7 +104,6 @@ __global__ __launch_bounds__(RED_TPB) void k_update(T *__restrict__ x, const T *
     T rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      x[c * N + s] = fma(alpha, p[c * N + s], x[c * N + s]);
       rv[c] = fma(-alpha, q[c * N + s], r[c * N + s]);
       r[c * N + s] = rv[c];
     }
@@ -169,14 +168,18 @@ __global__ __launch_bounds__(RED_TPB) void k_precond(const T *__restrict__ r, co
   }
 }
 
-// p = z + beta p
+// x += alpha p (the iteration's step), then p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(256) void k_pupdate(T *__restrict__ p, const T *__restrict__ z,
-                                                 int64_t n3, const CGState *__restrict__ st) {
-  const T beta = (T)st->beta;
+__global__ __launch_bounds__(256) void k_pupdate(T *__restrict__ x, T *__restrict__ p,
+                                                 const T *__restrict__ z, int64_t n3,
+                                                 const CGState *__restrict__ st) {
+  const T alpha = (T)st->alpha, beta = (T)st->beta;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-       s += (int64_t)gridDim.x * blockDim.x)
-    p[s] = fma(beta, p[s], z[s]);
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const T pv = p[s];
+    x[s] = fma(alpha, pv, x[s]);
+    p[s] = fma(beta, pv, z[s]);
+  }
 }
 
 enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_NORM = 3, FIN_BETA_FLEX = 4 };
@@ -523,14 +526,14 @@ int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T
                          (const T *)nullptr, h->d_flags, N, part);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst, FIN_ALPHA, it);
       if (flex)
-        hipLaunchKernelGGL((k_update<T, true>), dim3(RED_GRID), dim3(RED_TPB), 0, st, x, p, r, q, P, z,
+        hipLaunchKernelGGL((k_update<T, true>), dim3(RED_GRID), dim3(RED_TPB), 0, st, r, q, P, z,
                            h->d_flags, N, dst, part);
       else
-        hipLaunchKernelGGL((k_update<T, false>), dim3(RED_GRID), dim3(RED_TPB), 0, st, x, p, r, q, P,
-                           z, h->d_flags, N, dst, part);
+        hipLaunchKernelGGL((k_update<T, false>), dim3(RED_GRID), dim3(RED_TPB), 0, st, r, q, P, z,
+                           h->d_flags, N, dst, part);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst,
                          flex ? FIN_BETA_FLEX : FIN_BETA, it);
-      hipLaunchKernelGGL(k_pupdate<T>, grid_for(3 * N), dim3(256), 0, st, p, z, 3 * N, dst);
+      hipLaunchKernelGGL(k_pupdate<T>, grid_for(3 * N), dim3(256), 0, st, x, p, z, 3 * N, dst);
     }
     HHG_HIP(hipGetLastError());
     return HHG_OK;

@@ -270,14 +270,13 @@ def test_learned_blocks_match_oracle():
     LG.attach(lib, None)
 
 
-def test_training_gain_over_block_jacobi():
+@pytest.fixture(scope="module")
+def trained():
     """Records of rough errors (start vector x* + noise, iterates 0..2 of the
     plain solver) on a Carreau-viscosity eps-operator (cube24, level 4,
-    viscosity contrast near 1e3).  Training lowers the held-out one-step
-    smoothing error below block Jacobi's (the zero network); FCG with the
-    learned blocks reaches 1e-8.  Both iteration counts are printed: among
-    block-diagonal preconditioners block Jacobi minimises Kaporin's condition
-    number, so the learned blocks are not asserted to beat it in CG."""
+    viscosity contrast near 1e3), and a network trained on 12,000 of them;
+    the held-out loss of the zero network (block Jacobi) and of the trained
+    one on the other 2,000."""
     from paper_1908_08666_amd import Mesh
     from paper_1908_08666_amd import learned as LG
     mesh = Mesh(W.cube24(), 4, mu1=1.0)
@@ -300,13 +299,46 @@ def test_training_gain_over_block_jacobi():
     l1, _ = net.loss_grad(held, held.shape[0])
     print(f"  contrast {float(k.max() / k.min()):.1f}; held-out loss: block Jacobi {l0:.4f} -> "
           f"learned {l1:.4f}; train {hist[0]:.4f} -> {hist[-1]:.4f}", flush=True)
-    assert hist[-1] < hist[0]
-    assert l1 < l0
-    LG.attach(mesh, net)
+    return dict(mesh=mesh, k=k, b=b, xs=xs, net=net, l0=l0, l1=l1, hist=hist)
+
+
+def test_training_gain_over_block_jacobi(trained):
+    """Training lowers the held-out one-step smoothing error below block
+    Jacobi's (the zero network); FCG with the learned blocks reaches 1e-8.
+    Both iteration counts are printed: among block-diagonal preconditioners
+    block Jacobi minimises Kaporin's condition number, so the learned blocks
+    are not asserted to beat it in CG."""
+    from paper_1908_08666_amd import learned as LG
+    t = trained
+    mesh, k, b = t["mesh"], t["k"], t["b"]
+    assert t["hist"][-1] < t["hist"][0]
+    assert t["l1"] < t["l0"]
+    LG.attach(mesh, t["net"])
     _, ib = mesh.solve(b, k, precond="block_jacobi", solver="cg64", rtol=1e-8, check_every=8)
     xl, il = mesh.solve(b, k, precond="learned", solver="fcg64", rtol=1e-8, check_every=8)
     print(f"  iterations to 1e-8: block Jacobi PCG {ib['iterations']}, learned FCG "
           f"{il['iterations']}", flush=True)
     assert il["status"] == "HHG_OK" and il["rel_residual"] <= 1e-8
-    assert rel_err(xl.cpu().numpy(), xs.cpu().numpy()) <= 1e-6
+    assert rel_err(xl.cpu().numpy(), t["xs"].cpu().numpy()) <= 1e-6
     LG.attach(mesh, None)
+
+
+@pytest.mark.xfail(strict=True, reason="measured negative result: the pointwise 3x3 learned blocks "
+                   "lower the held-out one-step error by about 1 %, not 5 %, and do not cut CG "
+                   "iterations below block Jacobi's")
+def test_training_gain_reaches_five_percent(trained):
+    """The gain the learned smoother was meant to show: held-out one-step
+    error 5 % below block Jacobi's and fewer FCG iterations than block-Jacobi
+    PCG.  Expected to fail (strict): if it ever passes, the recorded negative
+    result is out of date."""
+    t = trained
+    from paper_1908_08666_amd import learned as LG
+    mesh, k, b = t["mesh"], t["k"], t["b"]
+    assert t["l1"] < 0.95 * t["l0"]
+    LG.attach(mesh, t["net"])
+    try:
+        _, ib = mesh.solve(b, k, precond="block_jacobi", solver="cg64", rtol=1e-8, check_every=8)
+        _, il = mesh.solve(b, k, precond="learned", solver="fcg64", rtol=1e-8, check_every=8)
+    finally:
+        LG.attach(mesh, None)
+    assert il["iterations"] < ib["iterations"]
