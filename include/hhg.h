@@ -249,15 +249,27 @@ int hhg_cg_solve(hhg_handle h, const hhg_solve_opts *o, const double *b, const d
  *     mu_i = eta_inf + (eta0 - eta_inf) (1 + kappa |eps(u)_i|^2)^r,
  * |eps|^2 = eps : eps.  Macro-interior nodes: gradient of the affine
  * least-squares fit over the 15-node patch (exact for quadratic u there).
- * Nodes on macro boundaries: volume-weighted mean of the gradients of all
- * elements at the node (the patch of the paper's quadratic fit on the lower
- * dimensional primitives is not specified).  u: FP64 [3][n] consistent device
- * vector, every node (Dirichlet ones included) used as given; k: FP64 [n]
- * device output, consistent.  workspace: hhg_viscosity_workspace_bytes bytes
- * of device memory.  Errors: HHG_EINVAL for null/misaligned pointers or
- * parameters outside eta0 >= eta_inf > 0, kappa >= 0.  Asynchronous.        */
+ * Nodes on macro boundaries (faces, edges, vertices), law->boundary =
+ * HHG_STRAIN_LSQ: least squares over the node's patch in the whole mesh (the
+ * node and all nodes sharing an element with it, in any macro) onto
+ * quadratics (eq. minimization_problem, m = 2), the gradient taken at the
+ * node; where the patch leaves that gradient undetermined (on the domain
+ * boundary, a one-sided patch) the affine fit over the same patch.  Exact
+ * for quadratic u at every node off the domain boundary.  The fit weights
+ * are built on the host at the handle's first call (patches of equal shape
+ * share them).  HHG_STRAIN_AVERAGE: volume-weighted mean of the gradients of
+ * all elements at the node (the averaging Sec. 3 names as the alternative).
+ * u: FP64 [3][n] consistent device vector, every node (Dirichlet ones
+ * included) used as given; k: FP64 [n] device output, consistent.
+ * workspace: hhg_viscosity_workspace_bytes bytes of device memory.  Errors:
+ * HHG_EINVAL for null/misaligned pointers, parameters outside
+ * eta0 >= eta_inf > 0, kappa >= 0, or an unknown boundary fit.
+ * Asynchronous.                                                              */
+enum hhg_strain_fit { HHG_STRAIN_LSQ = 0, HHG_STRAIN_AVERAGE = 1 };
 typedef struct {
   double eta0, eta_inf, kappa, r;
+  int32_t boundary;          /* hhg_strain_fit on macro-boundary nodes       */
+  int32_t pad;
 } hhg_carreau;
 
 int hhg_viscosity_workspace_bytes(hhg_handle h, size_t *bytes);

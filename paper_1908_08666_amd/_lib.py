@@ -14,6 +14,7 @@ HHG_DIRICHLET_OUTER, HHG_DIRICHLET_NONE = 0, 1
 HHG_CORR_PHYSICAL, HHG_CORR_NONE = 0, 1
 HHG_KHAT_PATCH, HHG_KHAT_EDGE = 0, 1
 HHG_IFACE_SYMMETRIC, HHG_IFACE_ROWWISE, HHG_IFACE_ZEROSUM = 0, 1, 2
+HHG_STRAIN_LSQ, HHG_STRAIN_AVERAGE = 0, 1
 HHG_METHOD_SCALED, HHG_METHOD_ONTHEFLY = 0, 1
 HHG_K_INTERIOR_SCALED, HHG_K_INTERIOR_ONTHEFLY, HHG_K_BOUNDARY_ROWS, HHG_K_GROUP_SUM = 0, 1, 2, 3
 KERNEL_NAMES = {0: "interior_scaled", 1: "interior_onthefly", 2: "boundary_rows", 3: "group_sum",
@@ -70,7 +71,7 @@ class TrainOpts(ctypes.Structure):
 
 class Carreau(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("eta_inf", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("r", ctypes.c_double)]
+                ("r", ctypes.c_double), ("boundary", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class TuneReport(ctypes.Structure):

@@ -57,6 +57,14 @@ struct hhg_ctx {
   int64_t *d_agrp_slot = nullptr;
   int64_t n_agrp = 0;
   hhg::StrainConst *d_stc = nullptr;
+  // strain-rate fit on macro-boundary nodes (built at the first viscosity
+  // call): per distinct node its patch (slots and gradient weights [3]) and
+  // the slots of its copies
+  bool lsq_built = false;
+  int64_t n_lsq = 0, n_lsq_affine = 0;
+  int64_t *d_lsq_ptr = nullptr, *d_lsq_slot = nullptr;
+  double *d_lsq_w = nullptr;
+  int64_t *d_lsq_optr = nullptr, *d_lsq_oslot = nullptr;
   uint8_t *d_flags = nullptr;
   hipStream_t side = nullptr;                // macro-boundary rows run here
   hipStream_t solve_stream = nullptr;        // solvers run (and capture graphs) here

@@ -392,6 +392,11 @@ void free_ctx(hhg_ctx *h) {
   dfree(h->d_agrp_ptr);
   dfree(h->d_agrp_slot);
   dfree(h->d_stc);
+  dfree(h->d_lsq_ptr);
+  dfree(h->d_lsq_slot);
+  dfree(h->d_lsq_w);
+  dfree(h->d_lsq_optr);
+  dfree(h->d_lsq_oslot);
   for (auto &r : h->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

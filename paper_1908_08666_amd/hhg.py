@@ -61,6 +61,10 @@ def _descriptors(verts, levels, mu0, lam0, mu1, lam1, coupling, dirichlet, corr,
     return md, od, (verts, lv)
 
 
+def _strain_fit(boundary):
+    return {"lsq": L.HHG_STRAIN_LSQ, "average": L.HHG_STRAIN_AVERAGE}[boundary]
+
+
 class Mesh:
     """Handle of a macro mesh with its operator (``hhg_setup_macro``).
 
@@ -194,8 +198,10 @@ class Mesh:
 
     # ------------------------------------------------------- viscosity
     def nodal_viscosity(self, u, eta0=1.0, eta_inf=1e-3, kappa=1.0, r=-0.25, k=None,
-                        workspace=None, stream=None):
-        """Carreau viscosity at the nodes from velocity u (``hhg_nodal_viscosity``)."""
+                        workspace=None, stream=None, boundary="lsq"):
+        """Carreau viscosity at the nodes from velocity u (``hhg_nodal_viscosity``);
+        boundary: "lsq" (least-squares fit on macro-boundary nodes) or
+        "average" (volume-weighted element gradients there)."""
         import torch
         N = self.n_nodes
         if k is None:
@@ -204,7 +210,7 @@ class Mesh:
         L.check(self._lib.hhg_viscosity_workspace_bytes(self._h, ctypes.byref(nb)))
         if workspace is None or workspace.numel() * workspace.element_size() < nb.value:
             workspace = torch.empty(int(nb.value) // 8 + 2, dtype=torch.float64, device=u.device)
-        law = L.Carreau(eta0, eta_inf, kappa, r)
+        law = L.Carreau(eta0, eta_inf, kappa, r, _strain_fit(boundary))
         L.check(self._lib.hhg_nodal_viscosity(self._h, _dev_ptr(u, (3, N), torch.float64),
                                               ctypes.byref(law), _dev_ptr(k, (N,), torch.float64),
                                               ctypes.c_void_p(workspace.data_ptr()),
@@ -466,9 +472,10 @@ class Multigrid:
 
     def stokes_picard(self, f, eta0, eta_inf, kappa, r, method="scaled", max_picard=100, nu1=3, nu2=3,
                       omega=0.7, omega_p=1.0, h=0.0, rtol=1e-3, maxit=500, stream=None,
-                      raise_on_status=True):
-        """Fixed-point iteration for the Carreau fluid (``hhg_mg_stokes_picard``).
-        Returns (u, p, mu, info dict)."""
+                      raise_on_status=True, boundary="lsq"):
+        """Fixed-point iteration for the Carreau fluid (``hhg_mg_stokes_picard``);
+        boundary: the strain-rate fit on macro-boundary nodes ("lsq" or
+        "average").  Returns (u, p, mu, info dict)."""
         import torch
         fm = self.meshes[-1]
         N = fm.n_nodes
@@ -476,7 +483,7 @@ class Multigrid:
         p = torch.empty((N,), dtype=torch.float64, device=f.device)
         mu = torch.empty((N,), dtype=torch.float64, device=f.device)
         o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit)
-        law = L.Carreau(float(eta0), float(eta_inf), float(kappa), float(r))
+        law = L.Carreau(float(eta0), float(eta_inf), float(kappa), float(r), _strain_fit(boundary))
         m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
         info = L.PicardInfo()
         rc = self._lib.hhg_mg_stokes_picard(self._mg, ctypes.byref(o), ctypes.byref(law), m, int(max_picard),

@@ -144,3 +144,21 @@ def test_picard_matches_oracle(method):
     assert abs(info["final_iterations"] - final) <= 1
     assert rel_err(ug[unk], uo[unk]) <= 1e-6 and rel_err(pg, po) <= 1e-6
     assert rel_err(mug, muo) <= 1e-8
+
+
+def test_physical_scaling_follows_nodal_integration_in_the_carreau_flow():
+    """Fig. stokes_profile: in the shear-thinning flow the viscosity and the
+    velocity of physical scaling follow those of nodal integration, while the
+    unphysical scaling departs from them (paper's Carreau parameters, force
+    1000 sin(2 pi x) e_z in the no-slip cube, level 4, line y = z = 1/2)."""
+    from paper_1908_08666_amd import carreau_profile as CP
+    res = CP.profiles(4)
+    for name, r in res["runs"].items():
+        print(f"  {name}: Picard {r['picard']} + {r['final_iterations']}, {r['status']}, "
+              f"viscosity {r['mu_range'][0]:.2f}..{r['mu_range'][1]:.2f}", flush=True)
+        assert r["status"] == "HHG_OK"
+    ph, un = res["physical_vs_nodal"], res["unphysical_vs_nodal"]
+    print(f"  deviation from nodal integration: physical mu {ph['mu']:.2e} speed {ph['speed']:.2e}; "
+          f"unphysical mu {un['mu']:.2e} speed {un['speed']:.2e}", flush=True)
+    assert res["runs"]["nodal"]["mu_range"][1] / res["runs"]["nodal"]["mu_range"][0] > 5.0
+    assert ph["mu"] < 0.25 * un["mu"] and ph["speed"] < 0.25 * un["speed"]

@@ -35,7 +35,9 @@ def test_quadratic_field_exact_in_macro_interiors():
     G = ST.nodal_gradients(mesh, u)
     inner = ~mesh.interface
     np.testing.assert_allclose(G[inner], gx[inner], atol=1e-12)
-    assert np.abs(G[~inner] - gx[~inner]).max() > 1e-3     # boundary average is not exact
+    # one macro: every boundary node is on the domain boundary, where the
+    # one-sided patch only allows the affine fit
+    assert np.abs(G[~inner] - gx[~inner]).max() > 1e-3
 
 
 def test_smooth_field_converges():
@@ -129,3 +131,106 @@ def test_strain_rate_of_rotation_is_zero():
     G = np.zeros((4, 3, 3))
     G[:, 0, 1], G[:, 1, 0] = 1.0, -1.0
     assert np.all(ST.strain_rate_squared(G) == 0)
+
+
+def _quadratic(x):
+    u = np.column_stack([x[:, 0] ** 2 + 3 * x[:, 1] * x[:, 2], x[:, 1] ** 2 - x[:, 0] * x[:, 2],
+                         2 * x[:, 2] ** 2 + x[:, 0] * x[:, 1]])
+    g = np.zeros((x.shape[0], 3, 3))
+    g[:, 0] = np.column_stack([2 * x[:, 0], 3 * x[:, 2], 3 * x[:, 1]])
+    g[:, 1] = np.column_stack([-x[:, 2], 2 * x[:, 1], -x[:, 0]])
+    g[:, 2] = np.column_stack([x[:, 1], x[:, 0], 4 * x[:, 2]])
+    return u, g
+
+
+@pytest.mark.parametrize("name,verts,L", [("kuhn6", W.kuhn6(), 3), ("cube24", W.cube24(), 2),
+                                          ("cube24", W.cube24(), 3)])
+def test_quadratic_fit_exact_on_macro_boundaries(name, verts, L):
+    """Sec. 3: the quadratic fit on the lower-dimensional primitives gives the
+    exact gradient of a quadratic field at every node off the domain
+    boundary (faces, edges, vertices of macros; on the 24-macro mesh their
+    patches are not point symmetric, and some edge patches determine only the
+    gradient, not the whole quadratic); the domain boundary falls back to
+    the affine fit; the element average is not exact there."""
+    mesh = MacroMesh(verts, L)
+    u, g = _quadratic(mesh.xyz - 0.3)
+    G = ST.nodal_gradients(mesh, u)
+    off = ~mesh.dirichlet
+    np.testing.assert_allclose(G[off], g[off], atol=1e-12)
+    deg = ST.boundary_fit_degrees(mesh)
+    assert np.all(deg[mesh.interface & off] == 2)
+    assert np.all(deg[mesh.dirichlet] == 1)
+    if name == "cube24":
+        Ga = ST.nodal_gradients(mesh, u, "average")
+        assert np.abs(Ga[mesh.interface & off] - g[mesh.interface & off]).max() > 1e-3
+
+
+def test_quadratic_and_affine_fits_agree_on_interior_patch():
+    """Sec. 3: on the point-symmetric 15-node patch of a macro-interior node
+    the quadratic and affine least-squares fits have the same gradient at the
+    node, for any data."""
+    mesh = MacroMesh(W.unit_tet(), 4)
+    ptr, nbr = ST.patches(mesh)
+    rng = np.random.default_rng(7)
+    inner = np.nonzero(~mesh.interface)[0]
+    for i in inner[::37]:
+        pts = np.concatenate([[i], nbr[ptr[i]:ptr[i + 1]]])
+        assert len(pts) == 15
+        U = rng.normal(size=(15, 3))
+        g2, ok2 = ST.fit_gradient(mesh.xyz[pts], U, 2)
+        g1, ok1 = ST.fit_gradient(mesh.xyz[pts], U, 1)
+        assert ok1 and ok2
+        np.testing.assert_allclose(g2, g1, atol=1e-10 * np.abs(g1).max())
+
+
+def test_quadratic_fit_converges_on_macro_boundaries():
+    """Off the domain boundary the fitted gradient of a smooth field
+    converges at second order on macro-boundary nodes too."""
+    def field(x):
+        return np.column_stack([np.sin(x[:, 0] + 2 * x[:, 1]), np.cos(x[:, 2] - x[:, 0]),
+                                np.sin(x[:, 1] * x[:, 2])])
+
+    def grad(x):
+        g = np.zeros((x.shape[0], 3, 3))
+        c0 = np.cos(x[:, 0] + 2 * x[:, 1])
+        s1 = np.sin(x[:, 2] - x[:, 0])
+        c2 = np.cos(x[:, 1] * x[:, 2])
+        g[:, 0, 0], g[:, 0, 1] = c0, 2 * c0
+        g[:, 1, 0], g[:, 1, 2] = s1, -s1
+        g[:, 2, 1], g[:, 2, 2] = x[:, 2] * c2, x[:, 1] * c2
+        return g
+
+    errs = []
+    for L in (3, 4):
+        mesh = MacroMesh(W.cube24(), L)
+        sel = mesh.interface & ~mesh.dirichlet
+        G = ST.nodal_gradients(mesh, field(mesh.xyz))
+        errs.append(np.abs(G[sel] - grad(mesh.xyz)[sel]).max())
+    assert errs[0] / errs[1] > 3.3
+
+
+def test_planted_fit_mistakes_are_caught(monkeypatch):
+    """A dropped cross term or an unscaled gradient in the quadratic fit
+    breaks the exactness pin on the macro boundaries."""
+    mesh = MacroMesh(W.cube24(), 2)
+    u, g = _quadratic(mesh.xyz)
+    sel = mesh.interface & ~mesh.dirichlet
+    orig = ST.fit_gradient
+
+    def no_cross(X, U, degree):
+        if degree != 2:
+            return orig(X, U, degree)
+        d = (X - X[0]) / np.abs(X - X[0]).max()
+        A = np.column_stack([np.ones(len(X)), d, d ** 2, d[:, 0] * d[:, 1], d[:, 0] * d[:, 2]])
+        coef = np.linalg.lstsq(A, U, rcond=None)[0]
+        return coef[1:4].T / np.abs(X - X[0]).max(), True
+
+    def unscaled(X, U, degree):
+        G, ok = orig(X, U, degree)
+        return (None if G is None else G * np.abs(X - X[0]).max()), ok
+
+    for bad in (no_cross, unscaled):
+        monkeypatch.setattr(ST, "fit_gradient", bad)
+        G = ST.nodal_gradients(mesh, u)
+        monkeypatch.undo()
+        assert np.abs(G[sel] - g[sel]).max() > 1e-3
