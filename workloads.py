@@ -87,6 +87,23 @@ def cube24() -> np.ndarray:
     return np.array(out, dtype=np.float64)
 
 
+def twod_mesh(name: str) -> np.ndarray:
+    """2-D macro triangulations (M, 3, 2): "triangle" (the unit right
+    triangle), "square" (the unit square cut along its anti-diagonal) and
+    "cross" (the unit square cut into four triangles through its centre,
+    so that one vertex is shared by four macros)."""
+    if name == "triangle":
+        return np.array([[[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]])
+    if name == "square":
+        return np.array([[[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]],
+                         [[1.0, 1.0], [0.0, 1.0], [1.0, 0.0]]])
+    if name == "cross":
+        c = [0.5, 0.5]
+        return np.array([[c, [0.0, 0.0], [1.0, 0.0]], [c, [1.0, 0.0], [1.0, 1.0]],
+                         [c, [1.0, 1.0], [0.0, 1.0]], [c, [0.0, 1.0], [0.0, 0.0]]])
+    raise ValueError(name)
+
+
 def batch_levels(n_problems: int = 256, lo: int = 3, hi: int = 6,
                  config_id: int = 4) -> np.ndarray:
     """Levels of the independent batched problems, uniform in lo..hi."""
