@@ -284,6 +284,46 @@ def learned_workload(dev, level=6, n_records=20000, epochs=100, batch=2048, lr=3
     return out
 
 
+def twod_workload(dev, level=12, steps=50):
+    """2-D apply (macro triangles, Sec. 2.3): the unit square as two macros
+    at the given level, E-form elasticity with an exp-Fourier coefficient;
+    scaled apply in FP64 and FP32 over 3 rotating input sets, HBM resident."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1908_08666_amd.twod import Mesh2D
+    mu, lam = W.eform_weights()
+    mesh = Mesh2D(W.twod_mesh("square"), level, mu1=mu, lam1=lam)
+    xy = mesh.coords().T
+    xyz = np.column_stack([xy, np.zeros(len(xy))])
+    out = dict(level=level, macros=2, slots=mesh.n_nodes, unknown_dofs=2 * mesh.n_unknown,
+               bytes_per_row=dict(f64=40, f32=20))
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        sets = []
+        for s in range(3):
+            rng = W.rng_for(6, s)
+            k = torch.from_numpy(W.exp_fourier_coefficient(xyz, rng, 16, 1.0)).to(dev, dt)
+            x = torch.from_numpy(rng.uniform(-1, 1, (2, mesh.n_nodes))).to(dev, dt)
+            sets.append((x, k, torch.empty_like(x)))
+        for q in range(6):
+            mesh.apply_scaled(*sets[q % 3])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for q in range(steps):
+            mesh.apply_scaled(*sets[q % 3])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        b = out["bytes_per_row"][name] * mesh.n_nodes
+        out[name] = dict(ms_per_apply=round(ms, 5), MDoF_s=round(2 * mesh.n_unknown / (ms * 1e-3) / 1e6, 1),
+                         GB_s=round(b / (ms * 1e-3) / 1e9, 1), hbm_frac=round(b / (ms * 1e-3) / 8e12, 3))
+        sets = None
+    mesh.close()
+    return out
+
+
 def batch_workload(dev, launches=20, count=10):
     """256 independent single-macro elasticity problems, levels uniform in
     3..6, each with its own coefficient field: FP32 apply over the whole
@@ -384,6 +424,7 @@ def main():
                     help="also run 256 independent uneven-level problems in one tuned, graph-replayed launch")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned block smoother and compare FCG solves (24 macros, level 6)")
+    ap.add_argument("--twod", action="store_true", help="2-D apply on the square (two macro triangles)")
     ap.add_argument("--carreau-profile", action="store_true",
                     help="physical / nodal / unphysical scaling in the Carreau fixed-point flow")
     ap.add_argument("--carreau-profile-level", type=int, default=5)
@@ -396,7 +437,7 @@ def main():
     args = ap.parse_args()
     if not args.quick:
         args.extra = args.solve = args.batch = args.learned = args.carreau = args.elastostatics = True
-        args.carreau_profile = True
+        args.carreau_profile = args.twod = True
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
               f"is not part of this build", file=sys.stderr)
@@ -570,6 +611,10 @@ def main():
         sets64 = sets32 = None
         torch.cuda.empty_cache()
         extra["carreau_cube24"] = carreau_workload(args.carreau_level, dev)
+
+    if args.twod:
+        torch.cuda.empty_cache()
+        extra["twod_square"] = twod_workload(dev)
 
     if args.carreau_profile:
         torch.cuda.empty_cache()

@@ -598,6 +598,49 @@ enum hhg_kernel_id {
 int hhg_profile_enable(hhg_handle h, int32_t on);
 int hhg_profile_read(hhg_handle h, int32_t kernel_id, int64_t *launches, double *total_ms);
 
+/* ---------------------------------------------------------------- 2-D
+ * The method on macro triangles (Sec. 2, Sec. 2.3): each macro triangle
+ * (vertices x0, x1, x2) is refined uniformly, 2^level intervals per edge;
+ * node (i, j), i + j <= n, lies at x0 + (i/n)(x1 - x0) + (j/n)(x2 - x0) and
+ * occupies slot off_m + j(n+1) - j(j-1)/2 + i, off_m = m (n+1)(n+2)/2.
+ * Vectors are [2][n_slots] (x, y) and [n_slots] (k); nodes shared by macros
+ * have one slot per macro, kept equal.  The operator is that of
+ * hhg_op_desc in two dimensions.  Physical scaling (Lemma, eq.
+ * correction2d): every edge of a macro-interior node has two elements, each
+ * the reflection of the other, so the scaled stencil reproduces nodal
+ * integration exactly (for any k) from the reference stencil, k at the
+ * 7-point patch and one correction constant per direction.  Rows of nodes on
+ * macro boundaries follow op->iface as in 3-D.
+ * Flags per slot: bit 0 Dirichlet, bit 1 owner, bit 2 on a macro boundary,
+ * bit 3 node with copies in other macros.                                  */
+typedef struct hhg2d_ctx *hhg2d_handle;
+typedef struct {
+  int32_t n_macro;
+  const double *verts;   /* host, [n_macro][3][2]                            */
+  int32_t level;         /* 1..13, common to all macros                      */
+  int32_t dirichlet;     /* HHG_DIRICHLET_OUTER: homogeneous on every macro
+                            edge met by one macro; HHG_DIRICHLET_NONE         */
+} hhg2d_mesh_desc;
+
+/* Set up a 2-D mesh and operator (host only; tables go to the device at the
+ * first apply).  Errors: HHG_EINVAL for a null argument, level outside
+ * 1..13, unknown options or a degenerate macro.                            */
+int hhg2d_setup(const hhg2d_mesh_desc *mesh, const hhg_op_desc *op, hhg2d_handle *out);
+int hhg2d_destroy(hhg2d_handle h);
+/* n_slots (vector length) and unknown nodes (distinct, non-Dirichlet).     */
+int hhg2d_layout(hhg2d_handle h, int64_t *n_slots, int64_t *n_unknown);
+/* Host outputs: coordinates [2][n_slots]; flags [n_slots] as above.        */
+int hhg2d_node_coords(hhg2d_handle h, double *xy);
+int hhg2d_node_flags(hhg2d_handle h, uint8_t *flags);
+/* y = A x on the device: prec HHG_F64 or HHG_F32 (x, k, y of that type),
+ * method HHG_METHOD_SCALED (scaled stencils on macro-interior rows) or
+ * HHG_METHOD_ONTHEFLY (nodal integration, eq. nodalquad, on every row).
+ * Dirichlet rows are zero and Dirichlet entries of x are read as 0; y is
+ * consistent over copies.  Asynchronous on `stream`.  Errors: HHG_EINVAL
+ * for null or misaligned pointers, y aliasing x or k, unknown options.      */
+int hhg2d_apply(hhg2d_handle h, int32_t prec, int32_t method, const void *x, const void *k, void *y,
+                void *stream);
+
 /* Text of the calling thread's last error ("" if none).                    */
 const char *hhg_last_error(void);
 

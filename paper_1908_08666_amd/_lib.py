@@ -36,6 +36,11 @@ class OpDesc(ctypes.Structure):
                 ("iface", ctypes.c_int32)]
 
 
+class MeshDesc2D(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int32), ("verts", ctypes.POINTER(ctypes.c_double)),
+                ("level", ctypes.c_int32), ("dirichlet", ctypes.c_int32)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precond", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
@@ -143,6 +148,12 @@ SIGNATURES = {
     "hhg_set_learned_model": ([_VP, _VP], ctypes.c_int),
     "hhg_preconditioner": ([_VP, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
     "hhg_preconditioner_noalloc": ([_VP, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "hhg2d_setup": ([ctypes.POINTER(MeshDesc2D), ctypes.POINTER(OpDesc), ctypes.POINTER(_VP)], ctypes.c_int),
+    "hhg2d_destroy": ([_VP], ctypes.c_int),
+    "hhg2d_layout": ([_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "hhg2d_node_coords": ([_VP, _VP], ctypes.c_int),
+    "hhg2d_node_flags": ([_VP, _VP], ctypes.c_int),
+    "hhg2d_apply": ([_VP, _I32, _I32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "hhg_mg_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(OpDesc), _I32, ctypes.POINTER(_VP)],
                       ctypes.c_int),
     "hhg_mg_destroy": ([_VP], ctypes.c_int),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhg.so")
 SOURCES = ["hhg_setup.cpp", "hhg_profile.cpp", "hhg_apply.hip", "hhg_solve.hip", "hhg_viscosity.hip",
-           "hhg_batch.hip", "hhg_learned.hip", "hhg_mg.hip",
+           "hhg_batch.hip", "hhg_learned.hip", "hhg_mg.hip", "hhg2d.hip",
            "hhg_interior_f64_scaled.hip", "hhg_interior_f64_onthefly.hip",
            "hhg_interior_f32_scaled.hip", "hhg_interior_f32_onthefly.hip"]
 ARCH = "gfx950"
