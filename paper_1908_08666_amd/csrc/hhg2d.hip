@@ -59,22 +59,6 @@ struct Macro2D {
                        // vertex e is (through another macro's edge, too)
 };
 
-struct Params {
-  int32_t scaled;      // 1: stencil scaling on macro-interior rows; 0: nodal integration
-  int32_t iface;       // hhg_iface for rows on macro boundaries
-  int32_t corr;        // 1: physical scaling, 0: unphysical
-  int32_t khat_edge;   // 1: khat = (k_i + k_j)/2
-};
-
-__device__ __forceinline__ int row_of(int ls, int n) {
-  // largest j with j(n+1) - j(j-1)/2 <= ls
-  const double b = 2.0 * n + 3.0;
-  int j = (int)((b - sqrt(b * b - 8.0 * (double)ls)) * 0.5);
-  j = max(0, min(j, n));
-  while (j > 0 && j * (n + 1) - j * (j - 1) / 2 > ls) --j;
-  while (j < n && (j + 1) * (n + 1) - (j + 1) * j / 2 <= ls) ++j;
-  return j;
-}
 
 __device__ __forceinline__ int slot_of(int i, int j, int n) { return j * (n + 1) - j * (j - 1) / 2 + i; }
 
@@ -86,36 +70,223 @@ __host__ __device__ __forceinline__ bool is_dirichlet(int i, int j, int n, uint3
          (((dmask >> 4) & 1u) && i == n && j == 0) || (((dmask >> 5) & 1u) && i == 0 && j == n);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply2d(const Macro2D *__restrict__ macros,
-                                                 const Const2D<T> *__restrict__ cs, Params P,
-                                                 const T *__restrict__ x, const T *__restrict__ kc,
-                                                 T *__restrict__ y, int64_t N) {
-  const int m = blockIdx.y;
-  const Macro2D M = macros[m];
-  const int n = M.n;
-  const int ls = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ls >= (n + 1) * (n + 2) / 2) return;
-  const int j = row_of(ls, n), i = ls - (j * (n + 1) - j * (j - 1) / 2);
-  const int64_t slot = M.off + ls;
-  if (is_dirichlet(i, j, n, M.dmask)) {
-    y[slot] = T(0);
-    y[N + slot] = T(0);
-    return;
+constexpr int TPB2 = 256;          // threads per block: columns i0 - 1 .. i0 + TPB2 - 2
+constexpr int OUT2 = TPB2 - 2;     // output columns per block
+constexpr int STRIP = 8;           // rows per block
+
+// third vertices of the two elements of edge d (the same on every macro;
+// the host setup checks its element tables against them)
+constexpr int P1[ND] = {2, 4, 0, 1, 2, 3};
+constexpr int P2[ND] = {5, 3, 4, 5, 1, 0};
+
+// Operator variant fixed at compile time: physical correction, unscaled
+// part present, k-hat as the edge mean.
+template <bool CORR, bool A0C, bool KEDGE>
+struct Var {};
+
+// Scaled entry of direction d applied to (e0, e1), accumulated into y.
+template <typename T, bool CORR, bool A0C, bool KEDGE, int D>
+__device__ __forceinline__ void scaled_entry(const T (&S)[ND][3], const T (&A)[ND][4], const T (&cc)[ND],
+                                             const T (&nk)[ND], T ck, T e0, T e1, T &y0, T &y1) {
+  const T kp1 = nk[P1[D]], kp2 = nk[P2[D]];
+  const T kh = KEDGE ? T(0.5) * (ck + nk[D]) : fma(ck + nk[D], T(1.0 / 3.0), (kp1 + kp2) * T(1.0 / 6.0));
+  const T s0 = fma(S[D][0], e0, S[D][2] * e1), s1 = fma(S[D][2], e0, S[D][1] * e1);
+  y0 = fma(kh, s0, y0);
+  y1 = fma(kh, s1, y1);
+  if constexpr (A0C) {
+    y0 = fma(A[D][0], e0, fma(A[D][2], e1, y0));
+    y1 = fma(A[D][1], e0, fma(A[D][3], e1, y1));
   }
-  const Const2D<T> &C = cs[m];
-  const T *X0 = x + M.off, *X1 = X0 + N, *K = kc + M.off;
-  const bool onb = i == 0 || j == 0 || i + j == n;
-  // neighbour values (x of Dirichlet nodes read as 0)
+  if constexpr (CORR) {
+    const T w = cc[D] * (kp1 - kp2);             // R[0][1] = w, R[1][0] = -w
+    y0 = fma(-w, e1, y0);
+    y1 = fma(w, e0, y1);
+  }
+}
+
+template <typename T, bool CORR, bool A0C, bool KEDGE, int D = 0>
+__device__ __forceinline__ void interior_row(const T (&S)[ND][3], const T (&A)[ND][4], const T (&cc)[ND],
+                                             const T (&nx0)[ND], const T (&nx1)[ND], const T (&nk)[ND],
+                                             T c0, T c1, T ck, T &y0, T &y1) {
+  scaled_entry<T, CORR, A0C, KEDGE, D>(S, A, cc, nk, ck, nx0[D] - c0, nx1[D] - c1, y0, y1);
+  if constexpr (D + 1 < ND)
+    interior_row<T, CORR, A0C, KEDGE, D + 1>(S, A, cc, nx0, nx1, nk, c0, c1, ck, y0, y1);
+}
+
+// Row of a node on a macro boundary (or any row of the on-the-fly method):
+// this macro's elements give nodal entries; under the symmetric and zero-sum
+// rules the entries towards macro-interior neighbours are the scaled ones.
+template <typename T, bool CORR, bool A0C, bool KEDGE>
+__device__ __forceinline__ void boundary_row2d(const Const2D<T> &C, int scaled, int iface, int i, int j,
+                                               int n, const T (&nx0)[ND], const T (&nx1)[ND],
+                                               const T (&nk)[ND], T c0, T c1, T ck, T &y0, T &y1) {
+  const auto &S = C.S;
+  const auto &A = C.A0;
+  const auto &cc = C.c;
   bool in[ND], nb_onb[ND];
-  T nx0[ND], nx1[ND], nk[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const int a = i + DI[d], b = j + DJ[d];
     in[d] = a >= 0 && b >= 0 && a + b <= n;
     nb_onb[d] = in[d] && (a == 0 || b == 0 || a + b == n);
+  }
+  const bool rowwise = !scaled || iface == HHG_IFACE_ROWWISE;
+  const bool zs = !rowwise && iface == HHG_IFACE_ZEROSUM;
+  y0 = T(0);
+  y1 = T(0);
+#pragma unroll
+  for (int t = 0; t < ND; ++t) {
+    const int da = TRI[t][0], db = TRI[t][1];
+    if (!(in[da] && in[db])) continue;
+    const T kb = (ck + nk[da] + nk[db]) * T(1.0 / 3.0);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      T e0, e1;
+      if (v == 0) {
+        if (zs) continue;
+        e0 = c0;
+        e1 = c1;
+      } else {
+        const int d = v == 1 ? da : db;
+        if (!rowwise && !nb_onb[d]) continue;   // scaled entry below
+        e0 = zs ? nx0[d] - c0 : nx0[d];
+        e1 = zs ? nx1[d] - c1 : nx1[d];
+      }
+      const T *B1 = C.E1[t][v], *B0 = C.E0[t][v];
+      y0 = fma(kb, fma(B1[0], e0, B1[2] * e1), fma(B0[0], e0, fma(B0[2], e1, y0)));
+      y1 = fma(kb, fma(B1[1], e0, B1[3] * e1), fma(B0[1], e0, fma(B0[3], e1, y1)));
+    }
+  }
+  if (rowwise) return;
+#define HHG2_SE(D)                                                                                    \
+  if (in[D] && !nb_onb[D])                                                                            \
+    scaled_entry<T, CORR, A0C, KEDGE, D>(S, A, cc, nk, ck, zs ? nx0[D] - c0 : nx0[D],                  \
+                                         zs ? nx1[D] - c1 : nx1[D], y0, y1);
+  HHG2_SE(0) HHG2_SE(1) HHG2_SE(2) HHG2_SE(3) HHG2_SE(4) HHG2_SE(5)
+#undef HHG2_SE
+}
+
+// Macro-interior rows (i, j >= 1, i + j <= n - 1).  A block sweeps a strip
+// of STRIP rows over OUT2 columns, RB rows at a time: the next RB rows of x
+// and k (one halo column each side; Dirichlet x zeroed) are staged into a
+// ring of RB + 2 rows in LDS, then the RB rows below them are computed from
+// the ring, so every value is read from HBM about once.
+// Grid: (column blocks, strips, macros).
+constexpr int RB = 2;
+constexpr int RING = RB + 2;
+
+template <typename T, bool CORR, bool A0C, bool KEDGE>
+__global__ __launch_bounds__(TPB2) void k_interior2d(const Macro2D *__restrict__ macros,
+                                                     const Const2D<T> *__restrict__ cs,
+                                                     const T *__restrict__ x, const T *__restrict__ kc,
+                                                     T *__restrict__ y, int64_t N) {
+  static_assert(STRIP % RB == 0, "whole batches per strip");
+  __shared__ T rx0[RING][TPB2], rx1[RING][TPB2], rk[RING][TPB2];
+  const Macro2D M = macros[blockIdx.z];
+  const int n = M.n;
+  const int i0 = blockIdx.x * OUT2, j0 = blockIdx.y * STRIP;
+  if (i0 + j0 > n) return;                   // strip outside the triangle (block-uniform)
+  const int t = threadIdx.x;
+  const int i = i0 - 1 + t;                  // column of this thread
+  const T *X0 = x + M.off, *X1 = X0 + N, *K = kc + M.off;
+  const Const2D<T> &C = cs[blockIdx.z];
+  // row j of this thread's column: global -> registers (nothing reads the
+  // values until put(), so the loads stay in flight through the compute of
+  // the rows below), then registers -> ring slot (j + RING) % RING
+  struct V3 {
+    T a, b, k;
+  };
+  auto fetch = [&](int j) {
+    V3 v{T(0), T(0), T(0)};
+    if (j >= 0 && j <= n && i >= 0 && i + j <= n) {
+      const int s = slot_of(i, j, n);
+      v.k = K[s];
+      v.a = X0[s];
+      v.b = X1[s];
+    }
+    return v;
+  };
+  auto put = [&](int j, const V3 &v) {
+    const int r = (j + RING) % RING;
+    const bool dz = j >= 0 && j <= n && i >= 0 && i + j <= n && is_dirichlet(i, j, n, M.dmask);
+    rx0[r][t] = dz ? T(0) : v.a;
+    rx1[r][t] = dz ? T(0) : v.b;
+    rk[r][t] = v.k;
+  };
+  const int j1 = min(j0 + STRIP, n);
+  {
+    V3 v[RB + 2];
+#pragma unroll
+    for (int q = 0; q < RB + 2; ++q) v[q] = fetch(j0 - 1 + q);
+#pragma unroll
+    for (int q = 0; q < RB + 2; ++q) put(j0 - 1 + q, v[q]);
+  }
+  for (int jb = j0; jb < j1; jb += RB) {
+    // the ring holds rows jb - 1 .. jb + RB; rows jb + RB + 1 .. jb + 2 RB
+    // are fetched now and written after the compute
+    const bool more = jb + RB < j1;
+    V3 nv[RB];
+    if (more)
+#pragma unroll
+      for (int q = 0; q < RB; ++q) nv[q] = fetch(jb + RB + 1 + q);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int j = jb + q;
+      if (j >= 1 && j < j1 && t >= 1 && t <= OUT2 && i >= 1 && i + j <= n - 1) {
+        const int rm = (j - 1 + RING) % RING, r0 = j % RING, rp = (j + 1) % RING;
+        T nx0[ND], nx1[ND], nk[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const int r = DJ[d] > 0 ? rp : (DJ[d] < 0 ? rm : r0);
+          const int c = t + DI[d];
+          nx0[d] = rx0[r][c];
+          nx1[d] = rx1[r][c];
+          nk[d] = rk[r][c];
+        }
+        T y0 = T(0), y1 = T(0);
+        interior_row<T, CORR, A0C, KEDGE>(C.S, C.A0, C.c, nx0, nx1, nk, rx0[r0][t], rx1[r0][t], rk[r0][t],
+                                          y0, y1);
+        const int64_t slot = M.off + slot_of(i, j, n);
+        y[slot] = y0;
+        y[N + slot] = y1;
+      }
+    }
+    __syncthreads();
+    if (more)
+#pragma unroll
+      for (int q = 0; q < RB; ++q) put(jb + RB + 1 + q, nv[q]);
+  }
+}
+
+// Macro-boundary rows (and, for the on-the-fly method, the interior rows
+// too): one thread per slot of the list, neighbours gathered from HBM.
+// bpos: packed (macro << 40 | j << 20 | i) of every listed slot.
+template <typename T, bool CORR, bool A0C, bool KEDGE>
+__global__ __launch_bounds__(256) void k_rows2d(const Macro2D *__restrict__ macros,
+                                                const Const2D<T> *__restrict__ cs,
+                                                const int64_t *__restrict__ bpos, int64_t nb, int scaled,
+                                                int iface, const T *__restrict__ x,
+                                                const T *__restrict__ kc, T *__restrict__ y, int64_t N) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nb) return;
+  const int64_t pk = bpos[q];
+  const int m = (int)(pk >> 40), j = (int)((pk >> 20) & 0xFFFFF), i = (int)(pk & 0xFFFFF);
+  const Macro2D M = macros[m];
+  const int n = M.n;
+  const int64_t slot = M.off + slot_of(i, j, n);
+  if (is_dirichlet(i, j, n, M.dmask)) {
+    y[slot] = T(0);
+    y[N + slot] = T(0);
+    return;
+  }
+  const T *X0 = x + M.off, *X1 = X0 + N, *K = kc + M.off;
+  T nx0[ND], nx1[ND], nk[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const int a = i + DI[d], b = j + DJ[d];
     nx0[d] = nx1[d] = nk[d] = T(0);
-    if (in[d]) {
+    if (a >= 0 && b >= 0 && a + b <= n) {
       const int s = slot_of(a, b, n);
       nk[d] = K[s];
       if (!is_dirichlet(a, b, n, M.dmask)) {
@@ -124,59 +295,10 @@ __global__ __launch_bounds__(256) void k_apply2d(const Macro2D *__restrict__ mac
       }
     }
   }
-  const T c0 = X0[ls], c1 = X1[ls], ck = K[ls];
-  T y0 = T(0), y1 = T(0);
-  // scaled entry of direction d applied to (e0, e1)
-  auto scaled = [&](int d, T e0, T e1) {
-    const T kp1 = nk[C.p1[d]], kp2 = nk[C.p2[d]];
-    const T kh = P.khat_edge ? T(0.5) * (ck + nk[d])
-                             : (ck + nk[d]) * T(1.0 / 3.0) + (kp1 + kp2) * T(1.0 / 6.0);
-    const T *S = C.S[d];
-    const T *A = C.A0[d];
-    y0 = fma(kh, fma(S[0], e0, S[2] * e1), y0);
-    y1 = fma(kh, fma(S[2], e0, S[1] * e1), y1);
-    y0 = fma(A[0], e0, fma(A[2], e1, y0));
-    y1 = fma(A[1], e0, fma(A[3], e1, y1));
-    if (P.corr) {
-      const T w = C.c[d] * (kp1 - kp2);          // R[0][1] = w, R[1][0] = -w
-      y0 = fma(-w, e1, y0);
-      y1 = fma(w, e0, y1);
-    }
-  };
-  if (P.scaled && !onb) {
-#pragma unroll
-    for (int d = 0; d < ND; ++d) scaled(d, nx0[d] - c0, nx1[d] - c1);
-  } else {
-    const bool rowwise = !P.scaled || P.iface == HHG_IFACE_ROWWISE;
-    const bool zs = !rowwise && P.iface == HHG_IFACE_ZEROSUM;
-#pragma unroll
-    for (int t = 0; t < ND; ++t) {
-      const int da = TRI[t][0], db = TRI[t][1];
-      if (!(in[da] && in[db])) continue;
-      const T kb = (ck + nk[da] + nk[db]) * T(1.0 / 3.0);
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        T e0, e1;
-        if (v == 0) {
-          if (zs) continue;
-          e0 = c0;
-          e1 = c1;
-        } else {
-          const int d = v == 1 ? da : db;
-          if (!rowwise && !nb_onb[d]) continue;   // scaled entry below
-          e0 = zs ? nx0[d] - c0 : nx0[d];
-          e1 = zs ? nx1[d] - c1 : nx1[d];
-        }
-        const T *B1 = C.E1[t][v], *B0 = C.E0[t][v];
-        y0 = fma(kb, fma(B1[0], e0, B1[2] * e1), fma(B0[0], e0, fma(B0[2], e1, y0)));
-        y1 = fma(kb, fma(B1[1], e0, B1[3] * e1), fma(B0[1], e0, fma(B0[3], e1, y1)));
-      }
-    }
-    if (!rowwise)
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-        if (in[d] && !nb_onb[d]) scaled(d, zs ? nx0[d] - c0 : nx0[d], zs ? nx1[d] - c1 : nx1[d]);
-  }
+  const int ls = slot_of(i, j, n);
+  T y0, y1;
+  boundary_row2d<T, CORR, A0C, KEDGE>(cs[m], scaled, iface, i, j, n, nx0, nx1, nk, X0[ls], X1[ls], K[ls],
+                                      y0, y1);
   y[slot] = y0;
   y[N + slot] = y1;
 }
@@ -247,6 +369,11 @@ struct hhg2d_ctx {
   hhg2::Const2D<double> *d_c64 = nullptr;
   hhg2::Const2D<float> *d_c32 = nullptr;
   int64_t *d_gptr = nullptr, *d_gslot = nullptr;
+  // row positions: the macro-boundary rows first (n_bpos of them), then the
+  // macro-interior rows (n_apos in all), for the element-row kernel
+  std::vector<int64_t> pos;
+  int64_t n_bpos = 0, n_apos = 0;
+  int64_t *d_pos = nullptr;
 };
 
 namespace hhg2 {
@@ -291,6 +418,7 @@ int ensure_device(hhg2d_ctx *h) {
   if ((rc = upload(&h->d_c32, c32.data(), c32.size()))) return rc;
   if ((rc = upload(&h->d_gptr, h->gptr.data(), h->gptr.size()))) return rc;
   if ((rc = upload(&h->d_gslot, h->gslot.data(), h->gslot.size()))) return rc;
+  if ((rc = upload(&h->d_pos, h->pos.data(), h->pos.size()))) return rc;
   h->on_device = true;
   h->device = dev;
   return HHG_OK;
@@ -307,6 +435,7 @@ void free_ctx(hhg2d_ctx *h) {
   f(h->d_c32);
   f(h->d_gptr);
   f(h->d_gslot);
+  f(h->d_pos);
   delete h;
 }
 
@@ -314,12 +443,31 @@ template <typename T>
 int apply_t(hhg2d_ctx *h, int method, const T *x, const T *k, T *y, hipStream_t st) {
   const Const2D<T> *cs;
   if constexpr (sizeof(T) == 8) cs = h->d_c64; else cs = h->d_c32;
-  Params P{method == HHG_METHOD_SCALED ? 1 : 0, h->op.iface, h->op.corr == HHG_CORR_PHYSICAL ? 1 : 0,
-           h->op.khat == HHG_KHAT_EDGE ? 1 : 0};
+  const int scaled = method == HHG_METHOD_SCALED ? 1 : 0, iface = h->op.iface;
+  const bool corr = h->op.corr == HHG_CORR_PHYSICAL, kedge = h->op.khat == HHG_KHAT_EDGE;
+  const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
   const int n = 1 << h->level;
-  const int64_t per = (int64_t)(n + 1) * (n + 2) / 2;
-  hipLaunchKernelGGL(k_apply2d<T>, dim3((unsigned)((per + 255) / 256), h->n_macro), dim3(256), 0, st,
-                     h->d_macros, cs, P, x, k, y, h->n_slots);
+  const dim3 grid((unsigned)((n + 1 + OUT2 - 1) / OUT2), (unsigned)((n + 1 + STRIP - 1) / STRIP),
+                  (unsigned)h->n_macro);
+  // the on-the-fly method takes every row through the element path
+  const int64_t nb = scaled ? h->n_bpos : h->n_apos;
+  const dim3 g2((unsigned)((nb + 255) / 256));
+#define HHG2_L(CR, A0, KE)                                                                              \
+  do {                                                                                                  \
+    if (scaled)                                                                                         \
+      hipLaunchKernelGGL((k_interior2d<T, CR, A0, KE>), grid, dim3(TPB2), 0, st, h->d_macros, cs, x, k, y, \
+                         h->n_slots);                                                                   \
+    hipLaunchKernelGGL((k_rows2d<T, CR, A0, KE>), g2, dim3(256), 0, st, h->d_macros, cs, h->d_pos, nb,   \
+                       scaled, iface, x, k, y, h->n_slots);                                             \
+  } while (0)
+  if (corr) {
+    if (a0) { if (kedge) HHG2_L(true, true, true); else HHG2_L(true, true, false); }
+    else { if (kedge) HHG2_L(true, false, true); else HHG2_L(true, false, false); }
+  } else {
+    if (a0) { if (kedge) HHG2_L(false, true, true); else HHG2_L(false, true, false); }
+    else { if (kedge) HHG2_L(false, false, true); else HHG2_L(false, false, false); }
+  }
+#undef HHG2_L
   const int64_t ng = (int64_t)h->gptr.size() - 1;
   if (ng > 0)
     hipLaunchKernelGGL(k_group2d<T>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, h->d_gptr,
@@ -439,6 +587,10 @@ int hhg2d_setup(const hhg2d_mesh_desc *mesh, const hhg_op_desc *op, hhg2d_handle
       // third vertices; (k_p1 - k_p2)/3 = kbar^t - kbar^{t^m} with t the first element
       C.p1[d] = TRI[ts[0]][2 - vs[0]];
       C.p2[d] = TRI[ts[1]][2 - vs[1]];
+      if (C.p1[d] != P1[d] || C.p2[d] != P2[d]) {
+        free_ctx(h);
+        return fail(HHG_EINVAL, "lattice check: third vertices of an edge differ from the kernel's table");
+      }
       // R = 1/2 (kbar^t - kbar^tm) asym(a_t) + 1/2 (kbar^tm - kbar^t) asym(a_tm),
       // asym(a_tm) = -asym(a_t): R = (k_p1 - k_p2)/3 asym(a_t); asym(a_t)[0][1] = (a[1] - a[2])/2
       C.c[d] = (a[1] - a[2]) / 6.0;
@@ -486,6 +638,16 @@ int hhg2d_setup(const hhg2d_mesh_desc *mesh, const hhg_op_desc *op, hhg2d_handle
     }
   }
   h->n_unknown = unknown;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int m = 0; m < M; ++m)
+      for (int j = 0; j <= n; ++j)
+        for (int i = 0; i + j <= n; ++i) {
+          const bool onb = i == 0 || j == 0 || i + j == n;
+          if (onb == (pass == 0)) h->pos.push_back(((int64_t)m << 40) | ((int64_t)j << 20) | i);
+        }
+  h->n_apos = (int64_t)h->pos.size();
+  h->n_bpos = 0;
+  for (int m = 0; m < M; ++m) h->n_bpos += 3 * (int64_t)n;
   *out = h;
   return HHG_OK;
 }

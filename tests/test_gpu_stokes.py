@@ -162,3 +162,4 @@ def test_physical_scaling_follows_nodal_integration_in_the_carreau_flow():
           f"unphysical mu {un['mu']:.2e} speed {un['speed']:.2e}", flush=True)
     assert res["runs"]["nodal"]["mu_range"][1] / res["runs"]["nodal"]["mu_range"][0] > 5.0
     assert ph["mu"] < 0.25 * un["mu"] and ph["speed"] < 0.25 * un["speed"]
+    assert ph["mu_l2"] < 0.25 * un["mu_l2"] and ph["speed_l2"] < 0.1 * un["speed_l2"]
