@@ -21,7 +21,7 @@ pytestmark = pytest.mark.skipif(
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(hhg_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(hhg(?:2d)?_\w+)\s*\(", text, re.M)))
 
 
 def test_exports_every_declared_symbol():
@@ -156,3 +156,36 @@ def test_bindings_mirror_the_header_structs():
     for cname, pyname in _STRUCTS.items():
         py = [f[0] for f in getattr(L, pyname)._fields_]
         assert py == structs[cname], (cname, py, structs[cname])
+
+
+@pytest.mark.parametrize("name,level", [("triangle", 3), ("square", 4), ("cross", 3)])
+def test_twod_layout_matches_oracle(name, level):
+    """2-D handle (host setup only): slot count, coordinates, Dirichlet flags,
+    one owner per distinct node and the unknown count against the 2-D
+    oracle's mesh."""
+    from scipy.spatial import cKDTree
+    from oracle import twod as T2
+    from paper_1908_08666_amd.twod import Mesh2D
+    mu, lam = W.eform_weights()
+    m = Mesh2D(W.twod_mesh(name), level, mu1=mu, lam1=lam)
+    orc = T2.Mesh2D(W.twod_mesh(name), level)
+    n = 1 << level
+    assert m.n_nodes == len(W.twod_mesh(name)) * (n + 1) * (n + 2) // 2
+    d, s2n = cKDTree(orc.xy).query(m.coords().T)
+    assert d.max() < 1e-12
+    fl = m.flags()
+    assert np.array_equal((fl & 1).astype(bool), orc.dirichlet[s2n])
+    assert np.array_equal(np.sort(s2n[(fl & 2) > 0]), np.arange(orc.n_nodes))
+    assert m.n_unknown == int((~orc.dirichlet).sum())
+    shared = np.bincount(s2n, minlength=orc.n_nodes) > 1
+    assert np.array_equal((fl & 8) > 0, shared[s2n] & ~orc.dirichlet[s2n])
+    m.close()
+
+
+def test_twod_rejects_bad_setup():
+    from paper_1908_08666_amd import _lib as L
+    from paper_1908_08666_amd.twod import Mesh2D
+    with pytest.raises(L.HHGError):
+        Mesh2D(W.twod_mesh("square"), 14, mu1=1.0)
+    with pytest.raises(L.HHGError):
+        Mesh2D(np.array([[[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]]]), 3, mu1=1.0)    # degenerate
