@@ -89,7 +89,7 @@ def consistent_random(mesh, rng, shape_first):
     return W.consistent_uniform(mesh.coords().T, (mesh.flags() & 2) > 0, rng, shape_first)
 
 
-def cpu_baseline(level=6, runs=10, seed=0):
+def cpu_baseline(level=6, runs=10, seed=0, cg_level=5):
     """The CPU oracle's apply on the host: the scaled operator of the same
     workload (6 Kuhn macros, E-form, k = exp(16-mode field)) assembled by the
     oracle from the Lemma at a level the host assembles in about a minute,
@@ -120,11 +120,25 @@ def cpu_baseline(level=6, runs=10, seed=0):
         t_omp.append(time.perf_counter() - t0)
     dofs = A.shape[0]
     cores = len(os.sched_getaffinity(0))
+    # block-Jacobi PCG to 1e-8 with SciPy on one core (the oracle's solver),
+    # on the same workload at a level that solves in seconds
+    from oracle import solvers as OS
+    orc_cg = MacroMesh(W.kuhn6(), cg_level)
+    k_cg = W.exp_fourier_coefficient(orc_cg.xyz, W.rng_for(2, 0), 16, 1.0)
+    A_cg = O.reduce_dirichlet(orc_cg, O.operator_matrix(orc_cg, k_cg, dict(mu1=mu, lam1=lam))).tocsr()
+    b_cg = np.random.default_rng(seed + 1).uniform(-1.0, 1.0, A_cg.shape[0])
+    t0 = time.perf_counter()
+    _, cg_it = OS.block_jacobi_cg(A_cg, b_cg, rtol=1e-8)
+    t_cg = time.perf_counter() - t0
     return dict(value=round(dofs / float(np.median(t_omp)) / 1e6, 2), unit="MDoF/s", cores=int(used),
                 kind="oracle", host_cores=cores,
                 scipy_1core=dict(value=round(dofs / float(np.median(t_sp)) / 1e6, 2), unit="MDoF/s",
                                  cores=1),
                 runs=runs, assembly_seconds=round(t_asm, 1), nnz=int(A.nnz), dofs=int(dofs),
+                cg=dict(level=cg_level, dofs=int(A_cg.shape[0]), iterations=int(cg_it),
+                        seconds=round(t_cg, 3), cores=1, rtol=1e-8,
+                        note="SciPy cg with the block-Jacobi preconditioner of the oracle's assembled "
+                             "operator (the oracle's solver), one core"),
                 sample=f"the same workload at level {level} (unknown DoFs {dofs}, {A.nnz} nonzeros, "
                        f"CSR {A.nnz * 12 / 1e6:.0f} MB): the oracle's assembled scaled operator, "
                        f"y = A x as a plain OpenMP CSR loop over {used} threads (value) and SciPy on "
@@ -595,6 +609,20 @@ def main():
         solves["mg_pcg64"] = mg_solve(W.kuhn6(), args.level, dict(mu1=mu, lam1=lam), k64, b)
         solves["mg_pcg64_f32cycle"] = mg_solve(W.kuhn6(), args.level, dict(mu1=mu, lam1=lam), k64, b,
                                                precision="f32")
+        # the same solver at the CPU baseline's CG level, for a like-for-like time
+        m5 = Mesh(W.kuhn6(), 5, mu1=mu, lam1=lam)
+        k5 = torch.from_numpy(W.exp_fourier_coefficient(m5.coords().T, W.rng_for(2, 0), 16, 1.0)).to(dev)
+        b5 = torch.from_numpy(consistent_random(m5, W.rng_for(2, 98), 3)).to(dev, torch.float64)
+        b5[:, (torch.from_numpy(m5.flags()).to(dev) & 1) > 0] = 0.0
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info5 = m5.solve(b5, k5, rtol=1e-8, check_every=16, solver="cg64")
+            torch.cuda.synchronize()
+            wall5 = time.perf_counter() - t0
+        solves["cg64_level5"] = dict(iterations=info5["iterations"], seconds=round(wall5, 4),
+                                     status=info5["status"], dofs=3 * m5.n_unknown)
+        m5 = None
         extra["solve_to_1e-8"] = solves
 
     if args.batch:

@@ -64,7 +64,7 @@ __device__ __forceinline__ void boundary_gather(const MacroInfo &mi, int i, int 
 // nodal centre term is dropped, so the centre block becomes minus the sum of
 // the row's other blocks.
 template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS>
-__device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilConst<T> &sc,
+__device__ __forceinline__ double boundary_row(const MacroInfo &mi, const StencilConst<T> &sc,
                                              const ElemConst<T> &ec, int i, int j, int k,
                                              const BoundaryNbr<T> &b,
                                              const uint8_t *__restrict__ flags,
@@ -140,6 +140,9 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
       }
     }
   }
+  // (x_i, this macro's part of the row): summed over the copies of a node
+  // this gives (x_i, (A x)_i), since x is the same in every copy
+  const double dot = (double)ci0 * (double)y0 + (double)ci1 * (double)y1 + (double)ci2 * (double)y2;
   // a node with copies in other macros is completed by the group sum
   if (RESID && !(flags[slot] & 8)) {
     y0 = f[slot] - y0;
@@ -149,6 +152,23 @@ __device__ __forceinline__ void boundary_row(const MacroInfo &mi, const StencilC
   y[slot] = y0;
   y[slot + nn] = y1;
   y[slot + 2 * nn] = y2;
+  return dot;
+}
+
+// Partial sum of a block of BOUNDARY_BLOCK threads written to part[3 b]
+// (part[3 b + 1], part[3 b + 2] = 0), reduced in a fixed order.
+__device__ __forceinline__ void block_part(double v, double *__restrict__ part, int b) {
+  __shared__ double red[BOUNDARY_BLOCK / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < BOUNDARY_BLOCK / 64; ++q) s += red[q];
+    part[3 * b] = s;
+    part[3 * b + 1] = 0.0;
+    part[3 * b + 2] = 0.0;
+  }
 }
 
 // Face coordinates: node (a, b) of layer l behind face f, and back.
@@ -206,7 +226,7 @@ constexpr int TILE_BYTES = (int)(2 * 4 * FT_P * sizeof(T));
 // HBM.  The rows of a block belong to one macro (bblk) and are ordered by the
 // boundary primitive they lie on, so that a wave rarely diverges; Dirichlet
 // slots (bit 30 in bijk) get their zero rows.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS>
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS, bool DOT>
 __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
                                             const MacroInfo *__restrict__ minfo,
                                             const StencilConst<T> *__restrict__ scs,
@@ -216,7 +236,7 @@ __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
                                             const uint8_t *__restrict__ flags,
                                             const T *__restrict__ x, const T *__restrict__ kc,
                                             const T *__restrict__ f, T *__restrict__ y,
-                                            int64_t nn) {
+                                            int64_t nn, double *__restrict__ part, int pb) {
   const int m = bblk[blk];
   const int packed = bijk[(int64_t)blk * BOUNDARY_BLOCK + threadIdx.x];
   const MacroInfo mi = minfo[m];
@@ -229,6 +249,11 @@ __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
       y[slot + nn] = T(0);
       y[slot + 2 * nn] = T(0);
     }
+    if (DOT && threadIdx.x == 0) {
+      part[3 * pb] = 0.0;
+      part[3 * pb + 1] = 0.0;
+      part[3 * pb + 2] = 0.0;
+    }
     return;
   }
   // the row's neighbour loads go out first, the constants' copies behind
@@ -238,17 +263,21 @@ __device__ __forceinline__ void listed_rows(int blk, unsigned char *smem,
   stage_constants(scs, ecs, m, smem);
   __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
   __syncthreads();
-  if (packed < 0) return;
-  if (packed & (1 << 30)) {                // Dirichlet slot: its row is zero
-    const int64_t slot = mi.off + plane_base32(mi.n, k) + (i + j) * (i + j + 1) / 2 + i;
-    y[slot] = T(0);
-    y[slot + nn] = T(0);
-    y[slot + 2 * nn] = T(0);
-    return;
+  double dot = 0.0;
+  if (packed >= 0) {
+    if (packed & (1 << 30)) {              // Dirichlet slot: its row is zero
+      const int64_t slot = mi.off + plane_base32(mi.n, k) + (i + j) * (i + j + 1) / 2 + i;
+      y[slot] = T(0);
+      y[slot + nn] = T(0);
+      y[slot + 2 * nn] = T(0);
+    } else {
+      const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(smem);
+      const StencilConst<T> &sc =
+          *reinterpret_cast<const StencilConst<T> *>(smem + sizeof(ElemConst<T>));
+      dot = boundary_row<T, RESID, ROWWISE, CORR, A0, ZS>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+    }
   }
-  const ElemConst<T> &ec = *reinterpret_cast<const ElemConst<T> *>(smem);
-  const StencilConst<T> &sc = *reinterpret_cast<const StencilConst<T> *>(smem + sizeof(ElemConst<T>));
-  boundary_row<T, RESID, ROWWISE, CORR, A0, ZS>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+  if constexpr (DOT) block_part(dot, part, pb);
 }
 
 // Displacement (da, db, dl) in face coordinates of lattice direction d for
@@ -276,7 +305,7 @@ __host__ __device__ constexpr int face_dl(int d) {
 // layer inside the macro and those in front of the face outside it, so with
 // the face fixed at compile time every neighbour's role and LDS offset is a
 // constant and the row needs no branches.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS, int FACE>
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS, bool DOT, int FACE>
 __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *smem,
                                           const MacroInfo *__restrict__ minfo,
                                           const StencilConst<T> *__restrict__ scs,
@@ -284,7 +313,7 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
                                           const uint8_t *__restrict__ flags,
                                           const T *__restrict__ x, const T *__restrict__ kc,
                                           const T *__restrict__ f, T *__restrict__ y,
-                                          int64_t nn) {
+                                          int64_t nn, double *__restrict__ part, int pb) {
   static_assert(FT_RPT * BOUNDARY_BLOCK == FT_W * FT_H && FT_H % FT_RPT == 0, "whole rows per thread");
   T(*tile)[4][FT_P] = reinterpret_cast<T(*)[4][FT_P]>(smem + CONST_BYTES<T>);  // [layer][x0 x1 x2 k]
   const int m = ft.macro;
@@ -325,6 +354,7 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
   __syncthreads();
+  double dot = 0.0;
 #pragma unroll 1
   for (int r = 0; r < FT_RPT; ++r) {       // rows b0 + tid / FT_W + r * FT_H / FT_RPT
     // the constants' LDS base is made opaque in every iteration, so that
@@ -358,8 +388,9 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
     nb.ci1 = tile[0][1][pc];
     nb.ci2 = tile[0][2][pc];
     nb.ck = tile[0][3][pc];
-    boundary_row<T, RESID, ROWWISE, CORR, A0, ZS>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
+    dot += boundary_row<T, RESID, ROWWISE, CORR, A0, ZS>(mi, sc, ec, i, j, k, nb, flags, f, y, nn);
   }
+  if constexpr (DOT) block_part(dot, part, pb);
 }
 
 // Rows of nodes on a macro boundary (Sec. 2.2).  Each copy of a node
@@ -370,19 +401,20 @@ __device__ __forceinline__ void face_rows(const FaceTile &ft, unsigned char *sme
 // the zero-sum centre.  One launch
 // covers all of them: the first nft blocks are face tiles, the rest blocks
 // of listed rows, so that the whole boundary is queued at once.
-template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS>
+template <typename T, bool RESID, bool ROWWISE, bool CORR, bool A0, bool ZS, bool DOT>
 __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const FaceTile *__restrict__ tiles, int nft,
     const int32_t *__restrict__ bijk, const int32_t *__restrict__ bblk,
     const uint8_t *__restrict__ flags, const T *__restrict__ x, const T *__restrict__ kc,
-    const T *__restrict__ f, T *__restrict__ y, int64_t nn) {
+    const T *__restrict__ f, T *__restrict__ y, int64_t nn, double *__restrict__ part) {
   __shared__ __align__(16) unsigned char smem[CONST_BYTES<T> + TILE_BYTES<T>];
   if ((int)blockIdx.x < nft) {
     const FaceTile ft = tiles[blockIdx.x];
     switch (__builtin_amdgcn_readfirstlane(ft.face)) {
 #define HHG_FR(F)                                                                                 \
-  face_rows<T, RESID, ROWWISE, CORR, A0, ZS, F>(ft, smem, minfo, scs, ecs, flags, x, kc, f, y, nn); \
+  face_rows<T, RESID, ROWWISE, CORR, A0, ZS, DOT, F>(ft, smem, minfo, scs, ecs, flags, x, kc, f, y, nn, \
+                                                    part, (int)blockIdx.x);                            \
   break
       case 0: HHG_FR(0);
       case 1: HHG_FR(1);
@@ -391,8 +423,8 @@ __global__ __launch_bounds__(BOUNDARY_BLOCK) void k_boundary_rows(
 #undef HHG_FR
     }
   } else
-    listed_rows<T, RESID, ROWWISE, CORR, A0, ZS>((int)blockIdx.x - nft, smem, minfo, scs, ecs, bijk,
-                                                 bblk, flags, x, kc, f, y, nn);
+    listed_rows<T, RESID, ROWWISE, CORR, A0, ZS, DOT>((int)blockIdx.x - nft, smem, minfo, scs, ecs, bijk,
+                                                      bblk, flags, x, kc, f, y, nn, part, (int)blockIdx.x);
 }
 
 // Sum of the partial rows of all copies of an interface node; the total (or
@@ -430,9 +462,10 @@ __global__ __launch_bounds__(256) void k_finish(const int64_t *__restrict__ ptr,
 // ------------------------------------------------------------ launchers
 namespace {
 
-template <typename T, bool RESID>
+template <typename T, bool RESID, bool DOT = false>
 int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, T *y,
-                    hipStream_t st) {
+                    hipStream_t st, double *part = nullptr) {
+  static_assert(!(DOT && RESID), "partial sums of (x, A x) only for the plain apply");
   const bool rowwise = method == METHOD_ONTHEFLY || h->op.iface == HHG_IFACE_ROWWISE;
   const bool zs = !rowwise && h->op.iface == HHG_IFACE_ZEROSUM;
   const bool corr = h->op.corr == HHG_CORR_PHYSICAL;
@@ -441,9 +474,9 @@ int launch_boundary(hhg_ctx *h, int method, const T *x, const T *k, const T *f, 
   if (nblk > 0) {
     const dim3 grid((unsigned)nblk);
 #define HHG_LB(RW, CR, A0, ZS)                                                                       \
-  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR, A0, ZS>), grid, dim3(BOUNDARY_BLOCK), 0, st, \
-                     h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_ftile, nft, h->d_bijk,              \
-                     h->d_bblk, h->d_flags, x, k, f, y, h->n_nodes)
+  hipLaunchKernelGGL((k_boundary_rows<T, RESID, RW, CR, A0, ZS, DOT>), grid, dim3(BOUNDARY_BLOCK), 0,  \
+                     st, h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_ftile, nft, h->d_bijk,          \
+                     h->d_bblk, h->d_flags, x, k, f, y, h->n_nodes, part)
 #define HHG_LB2(CR, A0) \
   if (zs) HHG_LB(false, CR, A0, true); else HHG_LB(false, CR, A0, false)
     ProfScope prof(h, HHG_K_BOUNDARY_ROWS, st);
@@ -507,6 +540,32 @@ int apply_t(hhg_ctx *h, int method, const T *f, const T *x, const T *k, T *y, hi
   return rc;
 }
 
+// y = A x and the partial sums of (x, y): the interior kernel writes one per
+// work item to part[0 .. n_work), the boundary-row kernel one per block to
+// part[n_work .. n_work + boundary blocks); summed in index order they give
+// (x, A x) over the owner copies of all nodes (each copy of an interface node
+// contributes x_i times its partial row).  Same streams as apply_t.
+template <typename T>
+int apply_dot_t(hhg_ctx *h, int method, const T *x, const T *k, T *y, double *part, hipStream_t st) {
+  double *pb = part + 3 * (int64_t)h->n_work;
+  auto interior = [&](hipStream_t s) {
+    return method == METHOD_SCALED ? launch_interior_dot<T, METHOD_SCALED>(h, x, k, y, part, s)
+                                   : launch_interior_dot<T, METHOD_ONTHEFLY>(h, x, k, y, part, s);
+  };
+  if (h->serial_apply) {
+    int rc = interior(st);
+    if (rc) return rc;
+    return launch_boundary<T, false, true>(h, method, x, k, nullptr, y, st, pb);
+  }
+  HHG_HIP(hipEventRecord(h->ev_fork, st));
+  HHG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  int rc = launch_boundary<T, false, true>(h, method, x, k, nullptr, y, h->side, pb);
+  if (!rc) rc = interior(st);
+  HHG_HIP(hipEventRecord(h->ev_join, h->side));
+  HHG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));
+  return rc;
+}
+
 bool overlaps(const void *a, const void *b, size_t bytes) {
   const char *pa = (const char *)a, *pb = (const char *)b;
   return pa < pb + bytes && pb < pa + bytes;
@@ -533,6 +592,20 @@ int apply_entry(hhg_ctx *h, int prec, int method, const void *f, const void *x, 
                            (double *)y, st);
   return apply_t<float>(h, method, (const float *)f, (const float *)x, (const float *)k,
                         (float *)y, st);
+}
+
+// Number of partial sums apply_dot_internal writes (3 doubles each).
+int64_t dot_parts(hhg_ctx *h) { return (int64_t)h->n_work + (int64_t)h->ftile.size() + (int64_t)h->bblk.size(); }
+
+// y = A x with the partial sums of (x, y) (see apply_dot_t); part holds
+// 3 dot_parts(h) doubles.
+int apply_dot_internal(hhg_ctx *h, int prec, int method, const void *x, const void *k, void *y,
+                       double *part, hipStream_t st) {
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  if (prec == HHG_F64)
+    return apply_dot_t<double>(h, method, (const double *)x, (const double *)k, (double *)y, part, st);
+  return apply_dot_t<float>(h, method, (const float *)x, (const float *)k, (float *)y, part, st);
 }
 
 // Operator application for the solvers: no argument checks beyond the

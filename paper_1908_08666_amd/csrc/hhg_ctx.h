@@ -60,6 +60,8 @@ struct hhg_ctx {
   // strain-rate fit on macro-boundary nodes (built at the first viscosity
   // call): per distinct node its patch (slots and gradient weights [3]) and
   // the slots of its copies
+  double *d_dotpart = nullptr;               // partial sums of the apply with (x, A x)
+  int64_t dotpart_cap = 0;                   // their capacity (in partial sums)
   bool lsq_built = false;
   int64_t n_lsq = 0, n_lsq_affine = 0;
   int64_t *d_lsq_ptr = nullptr, *d_lsq_slot = nullptr;

@@ -66,5 +66,7 @@ inline const ElemConst<float> *ec_ptr<float>(hhg_ctx *h) { return h->d_ec32; }
 // explicitly instantiated) in one translation unit per (T, METHOD).
 template <typename T, int METHOD, bool RESID>
 int launch_interior_v(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st);
+template <typename T, int METHOD>
+int launch_interior_dot(hhg_ctx *h, const T *x, const T *k, T *y, double *part, hipStream_t st);
 
 }  // namespace hhg

@@ -106,13 +106,14 @@ __device__ __forceinline__ void node_rows(const Node4<T> &c, const Node4<T> (&nb
 // One work item (a slab of NSUB * TPB positions over planes [ka, kb) of one
 // macro) computed by the whole workgroup, NSUB positions per thread (p0 + tid
 // + u TPB); every thread must call it (barriers).
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
+template <typename T, int METHOD, int OUT, bool CORR, bool A0, int NW, int TPB, int NSUB>
 __device__ __forceinline__ void interior_item(
     const WorkItem w, unsigned char *smem_raw,
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl) {
+    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part, int item) {
+  static_assert(OUT >= 0 && OUT <= 2, "output: 0 apply, 1 residual, 2 apply and (x, y) partial sum");
   Pair<T> *bufA = reinterpret_cast<Pair<T> *>(smem_raw);   // 3 planes of (x0, x1)
   Pair<T> *bufB = bufA + 3 * wl;                             // 3 planes of (x2, k)
   const MacroInfo mi = minfo[w.macro];
@@ -175,6 +176,7 @@ __device__ __forceinline__ void interior_item(
     }
   };
 
+  double dot_acc = 0.0;                  // OUT == 2: this thread's rows of (x, A x)
   Node4<T> pre[NW];
   {
     // the first three planes in one round of loads
@@ -238,6 +240,8 @@ __device__ __forceinline__ void interior_item(
         __builtin_amdgcn_sched_barrier(0);
         T y0, y1, y2;
         node_rows<T, METHOD, CORR, A0>(c, nb, scs[w.macro], ecs[w.macro], y0, y1, y2);
+        if constexpr (OUT == 2)
+          dot_acc += (double)c.x0 * (double)y0 + (double)c.x1 * (double)y1 + (double)c.x2 * (double)y2;
         yv[u][0] = y0;
         yv[u][1] = y1;
         yv[u][2] = y2;
@@ -251,7 +255,7 @@ __device__ __forceinline__ void interior_item(
     for (int u = 0; u < NSUB; ++u)
       if (act[u]) {
         const int64_t g = gk + ps_[u];
-        if constexpr (RESID) {
+        if constexpr (OUT == 1) {
           y[g] = f[g] - yv[u][0];
           y[g + nn] = f[g + nn] - yv[u][1];
           y[g + 2 * nn] = f[g + 2 * nn] - yv[u][2];
@@ -263,20 +267,42 @@ __device__ __forceinline__ void interior_item(
       }
     __syncthreads();
   }
+  if constexpr (OUT == 2) {
+    // the item's partial sum, reduced in a fixed order (deterministic)
+    __shared__ double red[TPB / 64];
+    for (int off = 32; off > 0; off >>= 1) dot_acc += __shfl_down(dot_acc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = dot_acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int q = 0; q < TPB / 64; ++q) s += red[q];
+      part[3 * item] = s;
+      part[3 * item + 1] = 0.0;
+      part[3 * item + 2] = 0.0;
+    }
+    __syncthreads();
+  }
 }
 
 // One workgroup per work item.
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
+template <typename T, int METHOD, int OUT, bool CORR, bool A0, int NW, int TPB, int NSUB>
 __global__ __launch_bounds__(TPB) void k_interior(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl) {
+    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const WorkItem w = work[blockIdx.x];
-  if (w.macro < 0) return;                  // padding item of the XCD-aware order
-  interior_item<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc, f,
-                                                           y, nn, wl);
+  if (w.macro < 0) {                        // padding item of the XCD-aware order
+    if (OUT == 2 && threadIdx.x == 0) {
+      part[3 * blockIdx.x] = 0.0;
+      part[3 * blockIdx.x + 1] = 0.0;
+      part[3 * blockIdx.x + 2] = 0.0;
+    }
+    return;
+  }
+  interior_item<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc, f,
+                                                         y, nn, wl, part, blockIdx.x);
 }
 
 // Persistent form: a grid of resident workgroups walks the work list with a
@@ -284,41 +310,47 @@ __global__ __launch_bounds__(TPB) void k_interior(
 // that is a multiple of the XCD count every item keeps the XCD that the
 // list's order assigns it.  Every workgroup leaves after at most
 // ceil(n_work / gridDim.x) items.
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
+template <typename T, int METHOD, int OUT, bool CORR, bool A0, int NW, int TPB, int NSUB>
 __global__ __launch_bounds__(TPB) void k_interior_persist(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work, int n_work,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl) {
+    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   for (int q = blockIdx.x; q < n_work; q += gridDim.x) {
     const WorkItem w = work[q];
     if (w.macro >= 0)                       // block-uniform
-      interior_item<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc,
-                                                               f, y, nn, wl);
+      interior_item<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc,
+                                                             f, y, nn, wl, part, q);
+    else if (OUT == 2 && threadIdx.x == 0) {
+      part[3 * q] = 0.0;
+      part[3 * q + 1] = 0.0;
+      part[3 * q + 2] = 0.0;
+    }
     __syncthreads();
   }
 }
 
 
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0, int NW, int TPB, int NSUB>
-int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
+template <typename T, int METHOD, int OUT, bool CORR, bool A0, int NW, int TPB, int NSUB>
+int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, double *part,
+                       hipStream_t st) {
   const int wl = h->wl_max;
   const size_t lds = 6 * (size_t)wl * sizeof(Pair<T>);
   ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
   if (h->persist_blocks > 0) {
-    auto kern = k_interior_persist<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>;
+    auto kern = k_interior_persist<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>;
     if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(std::min(h->persist_blocks, h->n_work)), dim3(TPB), lds, st,
                        h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_work, h->n_work, x, k, f, y,
-                       h->n_nodes, wl);
+                       h->n_nodes, wl, part);
   } else {
-    auto kern = k_interior<T, METHOD, RESID, CORR, A0, NW, TPB, NSUB>;
+    auto kern = k_interior<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>;
     if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
-                       ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl);
+                       ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl, part);
   }
   HHG_HIP(hipGetLastError());
   return HHG_OK;
@@ -326,23 +358,38 @@ int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hip
 
 // Positions per work item (= threads): 256; window entries per thread: up
 // to 2 (levels <= 7) or up to 6 (level 8).
-template <typename T, int METHOD, bool RESID, bool CORR, bool A0>
-int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
+template <typename T, int METHOD, int OUT, bool CORR, bool A0>
+int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, double *part,
+                    hipStream_t st) {
   if (h->n_work == 0) return HHG_OK;
   const int nw = (h->wl_max + 255) / 256;
-  if (nw <= 2) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 2, 256, 1>(h, x, k, f, y, st);
-  if (nw <= 6) return launch_interior_nw<T, METHOD, RESID, CORR, A0, 6, 256, 1>(h, x, k, f, y, st);
+  if (nw <= 2) return launch_interior_nw<T, METHOD, OUT, CORR, A0, 2, 256, 1>(h, x, k, f, y, part, st);
+  if (nw <= 6) return launch_interior_nw<T, METHOD, OUT, CORR, A0, 6, 256, 1>(h, x, k, f, y, part, st);
   return fail(HHG_EINVAL, "interior window larger than supported");
+}
+
+template <typename T, int METHOD, int OUT>
+int launch_interior_o(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, double *part,
+                      hipStream_t st) {
+  const bool corr = METHOD == METHOD_SCALED && h->op.corr == HHG_CORR_PHYSICAL;
+  const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
+  if (corr && a0) return launch_interior<T, METHOD, OUT, true, true>(h, x, k, f, y, part, st);
+  if (corr) return launch_interior<T, METHOD, OUT, true, false>(h, x, k, f, y, part, st);
+  if (a0) return launch_interior<T, METHOD, OUT, false, true>(h, x, k, f, y, part, st);
+  return launch_interior<T, METHOD, OUT, false, false>(h, x, k, f, y, part, st);
 }
 
 template <typename T, int METHOD, bool RESID>
 int launch_interior_v(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st) {
-  const bool corr = METHOD == METHOD_SCALED && h->op.corr == HHG_CORR_PHYSICAL;
-  const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
-  if (corr && a0) return launch_interior<T, METHOD, RESID, true, true>(h, x, k, f, y, st);
-  if (corr) return launch_interior<T, METHOD, RESID, true, false>(h, x, k, f, y, st);
-  if (a0) return launch_interior<T, METHOD, RESID, false, true>(h, x, k, f, y, st);
-  return launch_interior<T, METHOD, RESID, false, false>(h, x, k, f, y, st);
+  return launch_interior_o<T, METHOD, RESID ? 1 : 0>(h, x, k, f, y, nullptr, st);
+}
+
+// y = A x on the macro-interior rows and, per work item q, the partial sum
+// of (x, y) over its rows in part[3 q] (part[3 q + 1], part[3 q + 2] = 0):
+// h->n_work items.
+template <typename T, int METHOD>
+int launch_interior_dot(hhg_ctx *h, const T *x, const T *k, T *y, double *part, hipStream_t st) {
+  return launch_interior_o<T, METHOD, 2>(h, x, k, nullptr, y, part, st);
 }
 
 

@@ -6,4 +6,6 @@ template int launch_interior_v<float, METHOD_SCALED, false>(hhg_ctx *, const flo
                                                  const float *, float *, hipStream_t);
 template int launch_interior_v<float, METHOD_SCALED, true>(hhg_ctx *, const float *, const float *,
                                                 const float *, float *, hipStream_t);
+template int launch_interior_dot<float, METHOD_SCALED>(hhg_ctx *, const float *, const float *, float *, double *,
+                                                  hipStream_t);
 }  // namespace hhg

@@ -6,4 +6,6 @@ template int launch_interior_v<double, METHOD_SCALED, false>(hhg_ctx *, const do
                                                  const double *, double *, hipStream_t);
 template int launch_interior_v<double, METHOD_SCALED, true>(hhg_ctx *, const double *, const double *,
                                                 const double *, double *, hipStream_t);
+template int launch_interior_dot<double, METHOD_SCALED>(hhg_ctx *, const double *, const double *, double *, double *,
+                                                  hipStream_t);
 }  // namespace hhg

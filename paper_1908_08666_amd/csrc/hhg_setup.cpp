@@ -392,6 +392,7 @@ void free_ctx(hhg_ctx *h) {
   dfree(h->d_agrp_ptr);
   dfree(h->d_agrp_slot);
   dfree(h->d_stc);
+  dfree(h->d_dotpart);
   dfree(h->d_lsq_ptr);
   dfree(h->d_lsq_slot);
   dfree(h->d_lsq_w);

@@ -27,6 +27,9 @@ namespace hhg {
 
 int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
                    void *y, hipStream_t st);
+int apply_dot_internal(hhg_ctx *h, int prec, int method, const void *x, const void *k, void *y,
+                       double *part, hipStream_t st);
+int64_t dot_parts(hhg_ctx *h);
 int learned_precond(hhg_ctx *h, const double *k, double *P, uint16_t *feat, float *mout,
                     hipStream_t st);
 
@@ -506,6 +509,16 @@ int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T
   run = 0;
   int rc = apply_internal(h, prec, method, b, x, k, r, st);  // r = b - A x
   if (rc) return rc;
+  // partial sums of (p, A p) from the apply itself (allocated here, before
+  // any graph capture, and kept by the handle)
+  const int64_t nparts = dot_parts(h);
+  if (h->dotpart_cap < nparts) {
+    if (h->d_dotpart) HHG_HIP(hipFree(h->d_dotpart));
+    h->d_dotpart = nullptr;
+    h->dotpart_cap = 0;
+    HHG_HIP(hipMalloc((void **)&h->d_dotpart, 3 * (size_t)nparts * sizeof(double)));
+    h->dotpart_cap = nparts;
+  }
   {
     ProfScope ps(h, HHG_K_SOLVER_VECTOR, st);
     hipLaunchKernelGGL(k_precond<T>, dim3(RED_GRID), dim3(RED_TPB), 0, st, r, P, z, p, h->d_flags, N, part);
@@ -519,12 +532,12 @@ int pcg(hhg_ctx *h, int method, bool flex, const T *b, const T *k, T *x, T *r, T
 
   auto body = [&](int nit) -> int {
     for (int it = 0; it < nit; ++it) {
-      int rc2 = apply_internal(h, prec, method, nullptr, p, k, q, st);  // q = A p
+      // q = A p with the partial sums of (p, q)
+      int rc2 = apply_dot_internal(h, prec, method, p, k, q, h->d_dotpart, st);
       if (rc2) return rc2;
       ProfScope ps(h, HHG_K_SOLVER_VECTOR, st);
-      hipLaunchKernelGGL(k_dot2<T>, dim3(RED_GRID), dim3(RED_TPB), 0, st, p, q, (const T *)nullptr,
-                         (const T *)nullptr, h->d_flags, N, part);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, part, RED_GRID, dst, FIN_ALPHA, it);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_TPB), 0, st, h->d_dotpart, (int)nparts, dst,
+                         FIN_ALPHA, it);
       if (flex)
         hipLaunchKernelGGL((k_update<T, true>), dim3(RED_GRID), dim3(RED_TPB), 0, st, r, q, P, z,
                            h->d_flags, N, dst, part);
