@@ -442,6 +442,10 @@ def main():
     ap.add_argument("--carreau-profile", action="store_true",
                     help="physical / nodal / unphysical scaling in the Carreau fixed-point flow")
     ap.add_argument("--carreau-profile-level", type=int, default=5)
+    ap.add_argument("--elastostatics-finest", type=int, default=7,
+                    help="finest level of the elastostatics benchmark (8 is the paper's finest)")
+    ap.add_argument("--elastostatics-variants", default="",
+                    help="comma-separated subset of the elastostatics variants (default all)")
     ap.add_argument("--elastostatics", action="store_true",
                     help="also run the paper's manufactured-solution benchmark (V-cycles, levels 3..7)")
     ap.add_argument("--elastostatics-m", default="1,8",
@@ -664,11 +668,14 @@ def main():
             "physical_f32_cycles": dict(corr="physical", op_method="scaled", iface="rowwise",
                                         method="cycle", precision="f32"),
         }
+        if args.elastostatics_variants:
+            variants = {k: v for k, v in variants.items() if k in args.elastostatics_variants.split(",")}
+        fin = args.elastostatics_finest
+        lv = list(range(3, fin + 1))
         extra["elastostatics_kuhn6"] = dict(
-            levels=[3, 4, 5, 6, 7], finest=7, paper_levels=[1, 2, 3, 4, 5],
+            levels=lv, finest=fin, paper_levels=[q - 2 for q in lv],
             load="consistent mass matrix times the interpolated body force",
-            results=ELS.benchmark([3, 4, 5, 6, 7], 7,
-                                  ms=tuple(int(m) for m in args.elastostatics_m.split(",")),
+            results=ELS.benchmark(lv, fin, ms=tuple(int(m) for m in args.elastostatics_m.split(",")),
                                   variants=variants, dev=dev))
 
     cpu = None

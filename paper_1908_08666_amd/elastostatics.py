@@ -21,6 +21,7 @@ at level l is the Freudenthal lattice of mesh size h = 2^-l; the paper's
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -146,6 +147,8 @@ def benchmark(levels, finest, ms=(1, 2, 3, 8), variants=None, dev="cuda"):
                 for lev in levels:
                     u_h, info, secs = solve_level(lev, m, dev=dev, **kw)
                     err = fine.error(u_h, lev)
+                    print(f"elastostatics m={m} {name} level {lev}: error {err:.3e}, "
+                          f"{info['iterations']} iterations, {secs:.3f} s", file=sys.stderr, flush=True)
                     eoc = (float(np.log2(rows[-1]["error"] / err)) if rows else None)
                     rows.append(dict(level=lev, error=err, eoc=None if eoc is None else round(eoc, 3),
                                      iterations=info["iterations"], status=info["status"],
