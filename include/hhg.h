@@ -483,6 +483,14 @@ int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coar
 int hhg_mg_destroy(hhg_mg mg);
 /* handle of one level (owned by mg: do not destroy it) */
 int hhg_mg_level(hhg_mg mg, int32_t level, hhg_handle *out);
+/* Blocks of the damped smoother x += omega P (b - A x) on the levels above
+ * the coarsest (not in the paper): HHG_PRECOND_BLOCK_JACOBI (default,
+ * P = D^-1) or HHG_PRECOND_LEARNED (P = (I + M)^T D^-1 (I + M) of
+ * hhg_preconditioner, with the model attached to every one of those
+ * levels' handles by hhg_set_learned_model).  Takes effect at the next
+ * hhg_mg_setup_coefficient, which cycles and solves then require.  Errors:
+ * HHG_EINVAL for another preconditioner or a level without a model.        */
+int hhg_mg_set_smoother(hhg_mg mg, int32_t precond);
 int hhg_mg_workspace_bytes(hhg_mg mg, size_t *bytes);
 /* xf = P xc: xc on level fine_level - 1, xf on fine_level */
 int hhg_mg_prolong(hhg_mg mg, int32_t fine_level, const double *xc, double *xf, void *stream);

@@ -157,6 +157,7 @@ SIGNATURES = {
     "hhg_mg_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(OpDesc), _I32, ctypes.POINTER(_VP)],
                       ctypes.c_int),
     "hhg_mg_destroy": ([_VP], ctypes.c_int),
+    "hhg_mg_set_smoother": ([_VP, _I32], ctypes.c_int),
     "hhg_mg_level": ([_VP, _I32, ctypes.POINTER(_VP)], ctypes.c_int),
     "hhg_mg_workspace_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hhg_mg_prolong": ([_VP, _I32, _VP, _VP, _VP], ctypes.c_int),

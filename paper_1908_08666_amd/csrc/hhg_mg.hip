@@ -25,6 +25,7 @@ struct hhg_mg_s {
   int64_t *d_cu_owner = nullptr, *d_cu_ptr = nullptr, *d_cu_slot = nullptr;
   // host copy of the coarsest operator's inverse is rebuilt per coefficient
   std::vector<double> dense;
+  int smoother = HHG_PRECOND_BLOCK_JACOBI; // blocks of the smoother above the coarsest level
 };
 
 namespace hhg {
@@ -988,6 +989,19 @@ int hhg_mg_destroy(hhg_mg mg) {
   return HHG_OK;
 }
 
+int hhg_mg_set_smoother(hhg_mg mg, int32_t precond) {
+  if (!mg) return fail(HHG_EINVAL, "null argument");
+  if (precond != HHG_PRECOND_BLOCK_JACOBI && precond != HHG_PRECOND_LEARNED)
+    return fail(HHG_EINVAL, "smoother must be block Jacobi or learned");
+  if (precond == HHG_PRECOND_LEARNED)
+    for (size_t q = 1; q < mg->lev.size(); ++q)
+      if (!mg->lev[q]->model)
+        return fail(HHG_EINVAL, "learned smoother: attach a model to every level above the coarsest");
+  mg->smoother = precond;
+  mg->ready = nullptr;                     // blocks change: a new coefficient setup is needed
+  return HHG_OK;
+}
+
 int hhg_mg_level(hhg_mg mg, int32_t level, hhg_handle *out) {
   if (!mg || !out) return fail(HHG_EINVAL, "null argument");
   if (level < mg->coarse_level || level > mg->fine_level) return fail(HHG_EINVAL, "level out of range");
@@ -1044,9 +1058,10 @@ int hhg_mg_setup_coefficient(hhg_mg mg, int32_t method, const double *k, void *w
     HHG_HIP(hipGetLastError());
   }
   for (int q = 0; q < L; ++q) {
-    if ((rc = hhg_preconditioner(mg->lev[q], HHG_PRECOND_BLOCK_JACOBI, method, W.k[q], W.P[q],
-                                 st)))
-      return rc;
+    // the coarsest level is solved exactly; its blocks stay block Jacobi
+    const int pc = (mg->smoother == HHG_PRECOND_LEARNED && q > 0) ? HHG_PRECOND_LEARNED
+                                                                 : HHG_PRECOND_BLOCK_JACOBI;
+    if ((rc = hhg_preconditioner(mg->lev[q], pc, method, W.k[q], W.P[q], st))) return rc;
     // FP32 copies for FP32 cycles
     const int64_t N = mg->lev[q]->n_nodes;
     hipLaunchKernelGGL((k_cast<double, float>), grid1(N), dim3(256), 0, st, W.k[q], W.k32[q], N);

@@ -381,6 +381,16 @@ class Multigrid:
                                            _stream_ptr(stream)))
         return rc
 
+    def set_smoother(self, smoother="block_jacobi", net=None):
+        """Blocks of the damped smoother above the coarsest level
+        (``hhg_mg_set_smoother``): "block_jacobi", or "learned" with the
+        network ``net`` (a learned.SmootherNet) attached to those levels."""
+        from . import learned as LG
+        for q, mesh in enumerate(self.meshes):
+            LG.attach(mesh, net if (smoother == "learned" and q > 0) else None)
+        pc = {"block_jacobi": L.HHG_PRECOND_BLOCK_JACOBI, "learned": L.HHG_PRECOND_LEARNED}[smoother]
+        L.check(self._lib.hhg_mg_set_smoother(self._mg, pc))
+
     def setup_coefficient(self, k, method="scaled", stream=None):
         """Inject k (finest level, float64) and build every level's blocks
         and the coarse inverse for the scaled or the nodal-integration
