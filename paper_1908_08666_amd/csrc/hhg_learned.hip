@@ -268,15 +268,62 @@ __global__ __launch_bounds__(256) void k_train_record(const uint16_t *__restrict
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// One thread per parameter: its gradient summed over the batch (FP64), then
-// either stored (grad != null) or applied by an Adam step.  Thread 0 also
-// sums the loss partials of the batch into loss_out.
-__global__ __launch_bounds__(256) void k_grad_adam(const uint16_t *__restrict__ rec, int64_t B,
+// Gradient partial sums of one chunk of GCHUNK records, one workgroup per
+// chunk: the chunk's features, hidden activations and gradients are staged in
+// LDS, then each thread sums its parameters over the chunk's records in
+// FP64 (products of FP32 values are exact in FP64).  Parameter p of chunk c
+// goes to gpart[c * NPARAM + p].
+constexpr int GCHUNK = 64;
+__global__ __launch_bounds__(256) void k_grad_part(const uint16_t *__restrict__ rec, int64_t B,
                                                    const uint16_t *__restrict__ hid,
                                                    const float *__restrict__ d2,
                                                    const float *__restrict__ dz1,
-                                                   const double *__restrict__ part, int npart,
-                                                   double *__restrict__ loss_out,
+                                                   double *__restrict__ gpart) {
+  __shared__ float sf[GCHUNK][NIN];
+  __shared__ float sdz[GCHUNK][NHID];
+  __shared__ float shd[GCHUNK][NHID];
+  __shared__ float sd2[GCHUNK][NOUT];
+  const int64_t s0 = (int64_t)blockIdx.x * GCHUNK;
+  const int cnt = (int)min((int64_t)GCHUNK, B - s0);
+  for (int t = threadIdx.x; t < GCHUNK * NIN; t += blockDim.x) {
+    const int r = t / NIN, i = t % NIN;
+    sf[r][i] = r < cnt ? bf16_val(rec[(s0 + r) * REC_U16 + i]) : 0.0f;
+  }
+  for (int t = threadIdx.x; t < GCHUNK * NHID; t += blockDim.x) {
+    const int r = t / NHID, j = t % NHID;
+    sdz[r][j] = r < cnt ? dz1[(s0 + r) * NHID + j] : 0.0f;
+    shd[r][j] = r < cnt ? bf16_val(hid[(s0 + r) * NHID + j]) : 0.0f;
+  }
+  for (int t = threadIdx.x; t < GCHUNK * NOUT; t += blockDim.x) {
+    const int r = t / NOUT, o = t % NOUT;
+    sd2[r][o] = r < cnt ? d2[(s0 + r) * 16 + o] : 0.0f;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < NPARAM; p += blockDim.x) {
+    double g = 0.0;
+    if (p < OFF_B1) {
+      const int i = p / NHID, j = p % NHID;
+      for (int r = 0; r < cnt; ++r) g += (double)sf[r][i] * (double)sdz[r][j];
+    } else if (p < OFF_W2) {
+      const int j = p - OFF_B1;
+      for (int r = 0; r < cnt; ++r) g += (double)sdz[r][j];
+    } else if (p < OFF_B2) {
+      const int q = p - OFF_W2, j = q / NOUT, o = q % NOUT;
+      for (int r = 0; r < cnt; ++r) g += (double)shd[r][j] * (double)sd2[r][o];
+    } else {
+      const int o = p - OFF_B2;
+      for (int r = 0; r < cnt; ++r) g += (double)sd2[r][o];
+    }
+    gpart[(int64_t)blockIdx.x * NPARAM + p] = g;
+  }
+}
+
+// One thread per parameter: the chunk partials summed in chunk order (FP64),
+// then either stored (grad != null) or applied by an Adam step.  Thread 0
+// also sums the loss partials of the batch into loss_out.
+__global__ __launch_bounds__(256) void k_grad_adam(const double *__restrict__ gpart, int nchunk,
+                                                   int64_t B, const double *__restrict__ part,
+                                                   int npart, double *__restrict__ loss_out,
                                                    float *__restrict__ grad, float *__restrict__ w,
                                                    float *__restrict__ mom1, float *__restrict__ mom2,
                                                    float lr, float beta1, float beta2, float eps,
@@ -289,19 +336,7 @@ __global__ __launch_bounds__(256) void k_grad_adam(const uint16_t *__restrict__ 
   }
   if (p >= NPARAM) return;
   double g = 0.0;
-  if (p < OFF_B1) {
-    const int i = p / NHID, j = p % NHID;
-    for (int64_t s = 0; s < B; ++s) g += (double)bf16_val(rec[s * REC_U16 + i]) * dz1[s * NHID + j];
-  } else if (p < OFF_W2) {
-    const int j = p - OFF_B1;
-    for (int64_t s = 0; s < B; ++s) g += dz1[s * NHID + j];
-  } else if (p < OFF_B2) {
-    const int q = p - OFF_W2, j = q / NOUT, o = q % NOUT;
-    for (int64_t s = 0; s < B; ++s) g += (double)bf16_val(hid[s * NHID + j]) * d2[s * 16 + o];
-  } else {
-    const int o = p - OFF_B2;
-    for (int64_t s = 0; s < B; ++s) g += d2[s * 16 + o];
-  }
+  for (int c = 0; c < nchunk; ++c) g += gpart[(int64_t)c * NPARAM + p];
   const float gf = (float)g;
   if (grad) {
     grad[p] = gf;
@@ -456,7 +491,7 @@ struct TrainScratch {
   void *buf = nullptr;
   float *out = nullptr, *d2 = nullptr, *dz1 = nullptr;
   uint16_t *hid = nullptr;
-  double *part = nullptr, *loss = nullptr;
+  double *part = nullptr, *loss = nullptr, *gpart = nullptr;
   int nblk = 0;
   ~TrainScratch() {
     if (buf) (void)hipFree(buf);
@@ -467,7 +502,8 @@ struct TrainScratch {
     auto up = [&](size_t v) { return (v + a - 1) / a * a; };
     const size_t s_out = up(B * NOUT * 4), s_d2 = up(B * 16 * 4), s_dz = up(B * NHID * 4);
     const size_t s_hid = up(B * NHID * 2), s_part = up(nblk * 8), s_loss = up(nloss * 8);
-    HHG_HIP(hipMalloc(&buf, s_out + s_d2 + s_dz + s_hid + s_part + s_loss));
+    const size_t s_gpart = up((size_t)((B + GCHUNK - 1) / GCHUNK) * NPARAM * 8);
+    HHG_HIP(hipMalloc(&buf, s_out + s_d2 + s_dz + s_hid + s_part + s_loss + s_gpart));
     char *p = static_cast<char *>(buf);
     out = reinterpret_cast<float *>(p);
     p += s_out;
@@ -480,6 +516,8 @@ struct TrainScratch {
     part = reinterpret_cast<double *>(p);
     p += s_part;
     loss = reinterpret_cast<double *>(p);
+    p += s_loss;
+    gpart = reinterpret_cast<double *>(p);
     return HHG_OK;
   }
 };
@@ -502,9 +540,11 @@ int train_batch(hhg_mlp m, const uint16_t *rec, int64_t B, TrainScratch &ts, dou
     eps = o->eps;
   }
   const int npart = (int)((B + 255) / 256);   // partials written for this batch
-  hipLaunchKernelGGL(k_grad_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, rec, B, ts.hid,
-                     ts.d2, ts.dz1, ts.part, npart, loss_out, grad, m->w, m->m, m->v, lr, b1, b2,
-                     eps, c1, c2);
+  const int nchunk = (int)((B + GCHUNK - 1) / GCHUNK);
+  hipLaunchKernelGGL(k_grad_part, dim3(nchunk), dim3(256), 0, st, rec, B, ts.hid, ts.d2, ts.dz1,
+                     ts.gpart);
+  hipLaunchKernelGGL(k_grad_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, ts.gpart, nchunk, B,
+                     ts.part, npart, loss_out, grad, m->w, m->m, m->v, lr, b1, b2, eps, c1, c2);
   HHG_HIP(hipGetLastError());
   if (!grad) return pack(m, st);
   return HHG_OK;
