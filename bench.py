@@ -667,6 +667,8 @@ def main():
                                           method="cg"),
             "physical_f32_cycles": dict(corr="physical", op_method="scaled", iface="rowwise",
                                         method="cycle", precision="f32"),
+            "physical_variable_cycles": dict(corr="physical", op_method="scaled", iface="rowwise",
+                                             method="cycle", nu_inc=2),
         }
         if args.elastostatics_variants:
             variants = {k: v for k, v in variants.items() if k in args.elastostatics_variants.split(",")}

@@ -460,7 +460,7 @@ int hhg_set_learned_model(hhg_handle h, hhg_mlp m);
  * convergence).  Errors: HHG_EINVAL (null or misaligned pointer, level out of
  * range, mixed levels, non-conforming mesh, a workspace without coefficient
  * setup, coarse level with more than 512 unknown nodes, nu1 + nu2 < 1,
- * omega outside (0, 2), unknown method or precision), HHG_EHIP,
+ * omega outside (0, 2), nu_inc outside 0..8, unknown method or precision), HHG_EHIP,
  * HHG_EBREAKDOWN (singular coarse operator, or a breakdown of the solve),
  * HHG_ENOCONV (maxit reached; x and info are written).                     */
 typedef struct hhg_mg_s *hhg_mg;
@@ -477,6 +477,10 @@ typedef struct {
                           * rounded to FP32 on entry and z widened on exit,
                           * while the solve's residuals, dot products and
                           * updates stay FP64)                                */
+  int32_t nu_inc;        /* extra smoothing steps per level below the finest:
+                          * level q of the finest F smooths nu1 + nu_inc (F - q)
+                          * and nu2 + nu_inc (F - q) times (Sec. 5.2.1, the
+                          * variable V-cycle: 2); 0: the fixed V(nu1, nu2)     */
 } hhg_mg_opts;
 int hhg_mg_create(const hhg_mesh_desc *mesh, const hhg_op_desc *op, int32_t coarse_level,
                   hhg_mg *out);
@@ -553,7 +557,8 @@ typedef struct {
                           * unit-cube meshes, one macro edge of length 1)    */
   double rtol;           /* relative residual target                         */
   int32_t maxit;         /* Uzawa steps                                      */
-  int32_t pad;
+  int32_t nu_inc;        /* velocity cycle: extra smoothing steps per coarser
+                          * level, as hhg_mg_opts.nu_inc (the paper: 2)      */
 } hhg_stokes_opts;
 int hhg_mg_stokes_workspace_bytes(hhg_mg mg, size_t *bytes);
 int hhg_mg_stokes_solve(hhg_mg mg, const hhg_stokes_opts *o, const double *f, const double *g,

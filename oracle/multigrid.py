@@ -17,7 +17,8 @@ is checked against:
                      inverse 3x3 diagonal blocks.
 * ``vcycle``         one V(nu1, nu2) cycle: damped block-Jacobi smoothing,
                      residual restriction, coarse correction, smoothing; an
-                     exact solve on the coarsest level.
+                     exact solve on the coarsest level; optionally the
+                     variable cycle (more smoothing on coarser levels).
 * ``mg_pcg``         conjugate gradients preconditioned by one V-cycle.
 
 Reading: the paper smooths with a hybrid Gauss-Seidel; here the smoother is
@@ -140,18 +141,24 @@ class Hierarchy:
 
 
 def vcycle(H: Hierarchy, b: np.ndarray, level: int | None = None, nu1=3, nu2=3,
-           omega=0.7) -> np.ndarray:
-    """One V(nu1, nu2) cycle for A_level e = b from e = 0."""
-    q = len(H.A) - 1 if level is None else level
+           omega=0.7, nu_inc=0) -> np.ndarray:
+    """One V(nu1, nu2) cycle for A_level e = b from e = 0.  With nu_inc > 0
+    the variable V-cycle of Sec. 5.2.1: a level that lies j levels below the
+    finest smooths nu1 + j nu_inc times before and nu2 + j nu_inc times
+    after its coarse correction."""
+    finest = len(H.A) - 1
+    q = finest if level is None else level
     if q == 0:
         return H._coarse_lu.solve(b)
     A, Dinv, P = H.A[q], H.Dinv[q], H.P[q - 1]
+    pre = nu1 + nu_inc * (finest - q)
+    post = nu2 + nu_inc * (finest - q)
     x = np.zeros_like(b)
-    for _ in range(nu1):
+    for _ in range(pre):
         x = x + omega * (Dinv @ (b - A @ x))
     r = b - A @ x
-    x = x + P @ vcycle(H, P.T @ r, q - 1, nu1, nu2, omega)
-    for _ in range(nu2):
+    x = x + P @ vcycle(H, P.T @ r, q - 1, nu1, nu2, omega, nu_inc)
+    for _ in range(post):
         x = x + omega * (Dinv @ (b - A @ x))
     return x
 

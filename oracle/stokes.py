@@ -132,7 +132,7 @@ def schur_diag(mesh: MacroMesh, mu: np.ndarray, h: float) -> np.ndarray:
 
 
 def inexact_uzawa(H, mesh: MacroMesh, mu, f, g=None, h=None, u0=None, p0=None, omega_p=1.0,
-                  rtol=1e-8, maxit=500, cycles=1, nu1=3, nu2=3, omega=0.7):
+                  rtol=1e-8, maxit=500, cycles=1, nu1=3, nu2=3, omega=0.7, nu_inc=0):
     """Inexact Uzawa iteration for [[A, B^T], [B, C]] [u; p] = [f; g] on the
     finest level of the velocity hierarchy H (operator A = H.A[-1] on the
     unknown velocity DoFs, pressure on every node):
@@ -158,7 +158,7 @@ def inexact_uzawa(H, mesh: MacroMesh, mu, f, g=None, h=None, u0=None, p0=None, o
     hist = []
     for it in range(1, maxit + 1):
         for _ in range(cycles):
-            u = u + vcycle(H, f - A @ u - B.T @ p, nu1=nu1, nu2=nu2, omega=omega)
+            u = u + vcycle(H, f - A @ u - B.T @ p, nu1=nu1, nu2=nu2, omega=omega, nu_inc=nu_inc)
         p = p + omega_p * (B @ u + C @ p - g) / S
         p = p - (m @ p) / m.sum()
         ru = f - A @ u - B.T @ p

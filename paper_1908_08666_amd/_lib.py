@@ -63,7 +63,7 @@ HHG_SAMPLE_BYTES = 128
 class MgOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("nu_inc", ctypes.c_int32)]
 
 
 HHG_MG_CG, HHG_MG_CYCLE = 0, 1
@@ -93,7 +93,7 @@ HHG_STOKES_DIV, HHG_STOKES_GRAD, HHG_STOKES_STAB, HHG_STOKES_MASS = 0, 1, 2, 3
 class StokesOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("omega_p", ctypes.c_double), ("h", ctypes.c_double), ("rtol", ctypes.c_double),
-                ("maxit", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("maxit", ctypes.c_int32), ("nu_inc", ctypes.c_int32)]
 
 
 class PicardInfo(ctypes.Structure):

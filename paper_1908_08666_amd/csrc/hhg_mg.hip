@@ -458,7 +458,10 @@ int restrict_(hhg_mg_s *mg, int q, const T *rf, T *rc, hipStream_t st) {
 }
 
 // x_q = V-cycle applied to b_q (levels q and below), in the precision T
-// (operator, smoother and transfers in T; the coarse inverse is FP64)
+// (operator, smoother and transfers in T; the coarse inverse is FP64).
+// Level q of the finest F smooths nu1 + nu_inc (F - q) times before and
+// nu2 + nu_inc (F - q) times after the coarse correction (Sec. 5.2.1: the
+// variable V-cycle adds two steps per coarser level).
 template <typename T>
 int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const T *b, T *x,
            hipStream_t st) {
@@ -473,6 +476,8 @@ int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const T *
     return HHG_OK;
   }
   int rc;
+  const int extra = o.nu_inc * ((int)mg->lev.size() - 1 - q);
+  const int nu1 = o.nu1 + extra, nu2 = o.nu2 + extra;
   const LevelArrays<T> A = level_arrays<T>(W, q), C = level_arrays<T>(W, q - 1);
   T *r = A.r;
   const T omega = (T)o.omega;
@@ -487,14 +492,14 @@ int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const T *
     HHG_HIP(hipGetLastError());
     return HHG_OK;
   };
-  for (int s = 0; s < o.nu1; ++s)
+  for (int s = 0; s < nu1; ++s)
     if ((rc = smooth(s == 0))) return rc;
-  if (o.nu1 == 0) hipLaunchKernelGGL(k_fill0<T>, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
+  if (nu1 == 0) hipLaunchKernelGGL(k_fill0<T>, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
   if ((rc = apply_internal(h, prec_of<T>(), mg->method, b, x, A.k, r, st))) return rc;
   if ((rc = restrict_<T>(mg, q, r, C.b, st))) return rc;
   if ((rc = vcycle<T>(mg, W, o, q - 1, C.b, C.x, st))) return rc;
   if ((rc = prolong<T>(mg, q, C.x, x, true, st))) return rc;
-  for (int s = 0; s < o.nu2; ++s)
+  for (int s = 0; s < nu2; ++s)
     if ((rc = smooth(false))) return rc;
   return HHG_OK;
 }
@@ -579,6 +584,7 @@ int check_opts(const hhg_mg_opts *o) {
   if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 64 || o->nu2 > 64)
     return fail(HHG_EINVAL, "smoothing steps must be 0..64 each, at least one in total");
   if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(HHG_EINVAL, "omega must lie in (0, 2)");
+  if (o->nu_inc < 0 || o->nu_inc > 8) return fail(HHG_EINVAL, "nu_inc must be 0..8");
   if (o->method != HHG_MG_CG && o->method != HHG_MG_CYCLE)
     return fail(HHG_EINVAL, "unknown multigrid solve method");
   if (o->precision != HHG_F64 && o->precision != HHG_F32)
@@ -874,6 +880,7 @@ int uzawa(hhg_mg_s *mg, const MgWork &W, const StokesWork &S, const hhg_stokes_o
   hhg_mg_opts mo{};
   mo.nu1 = o.nu1;
   mo.nu2 = o.nu2;
+  mo.nu_inc = o.nu_inc;
   mo.omega = o.omega;
   mo.method = HHG_MG_CYCLE;
   mo.precision = HHG_F64;
@@ -1275,6 +1282,7 @@ int check_stokes(hhg_mg mg, const hhg_stokes_opts *o, const double *f, const dou
     return fail(HHG_EINVAL, "smoothing steps must be 0..64 each, at least one in total");
   if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(HHG_EINVAL, "omega must lie in (0, 2)");
   if (!(o->omega_p > 0.0 && o->omega_p < 4.0)) return fail(HHG_EINVAL, "omega_p must lie in (0, 4)");
+  if (o->nu_inc < 0 || o->nu_inc > 8) return fail(HHG_EINVAL, "nu_inc must be 0..8");
   if (!(o->rtol >= 0.0) || o->maxit < 0) return fail(HHG_EINVAL, "rtol must be >= 0 and maxit >= 0");
   return HHG_OK;
 }

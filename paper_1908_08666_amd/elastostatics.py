@@ -70,10 +70,12 @@ def consistent_load(xyz, F, level):
 
 
 def solve_level(level, m, corr="physical", iface="rowwise", method="cycle", op_method="scaled",
-                load="consistent", rtol=1e-8, maxit=200, coarse=2, precision="f64", dev="cuda"):
+                load="consistent", rtol=1e-8, maxit=200, coarse=2, precision="f64", nu_inc=0,
+                dev="cuda"):
     """Discrete solution on one level: (u_h [3, n_slots] with the boundary
     values, solve info, seconds of the solve).  precision: arithmetic of the
-    V-cycles ("f64" or "f32"; residuals and updates stay FP64)."""
+    V-cycles ("f64" or "f32"; residuals and updates stay FP64); nu_inc:
+    extra smoothing steps per coarser level (the variable V-cycle)."""
     import torch
     import workloads as W
     from .hhg import Mesh, Multigrid
@@ -97,7 +99,7 @@ def solve_level(level, m, corr="physical", iface="rowwise", method="cycle", op_m
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         w, info = mg.solve(b, rtol=rtol, maxit=maxit, method=method, precision=precision,
-                           raise_on_status=False)
+                           nu_inc=nu_inc, raise_on_status=False)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         return w + g, info, secs

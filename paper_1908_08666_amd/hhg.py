@@ -352,10 +352,10 @@ class Multigrid:
         return ctypes.c_void_p(base + ((-base) % 256))
 
     @staticmethod
-    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100, method="cg", precision="f64"):
+    def _opts(nu1, nu2, omega, rtol=1e-8, maxit=100, method="cg", precision="f64", nu_inc=0):
         m = {"cg": L.HHG_MG_CG, "cycle": L.HHG_MG_CYCLE}[method]
         p = {"f64": L.HHG_F64, "f32": L.HHG_F32}[precision]
-        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), m, p)
+        return L.MgOpts(int(nu1), int(nu2), float(omega), float(rtol), int(maxit), m, p, int(nu_inc))
 
     def prolong(self, fine_level, xc, xf=None, stream=None):
         """xf = P xc (``hhg_mg_prolong``)."""
@@ -402,21 +402,22 @@ class Multigrid:
         L.check(self._lib.hhg_mg_setup_coefficient(self._mg, m, _dev_ptr(k, (f.n_nodes,), torch.float64),
                                                     ws, _stream_ptr(stream)))
 
-    def vcycle(self, r, z=None, nu1=3, nu2=3, omega=0.7, precision="f64", stream=None):
+    def vcycle(self, r, z=None, nu1=3, nu2=3, omega=0.7, precision="f64", stream=None, nu_inc=0):
         """z = V(r) on the finest level (``hhg_mg_vcycle``); precision "f32"
-        runs the cycle in FP32 on rounded copies of r and z."""
+        runs the cycle in FP32 on rounded copies of r and z; nu_inc extra
+        smoothing steps per coarser level (the variable V-cycle: 2)."""
         import torch
         f = self.meshes[-1]
         if z is None:
             z = torch.empty_like(r)
-        o = self._opts(nu1, nu2, omega, precision=precision)
+        o = self._opts(nu1, nu2, omega, precision=precision, nu_inc=nu_inc)
         L.check(self._lib.hhg_mg_vcycle(self._mg, ctypes.byref(o), _dev_ptr(r, (3, f.n_nodes), torch.float64),
                                         _dev_ptr(z, (3, f.n_nodes), torch.float64),
                                         self._workspace(r.device), _stream_ptr(stream)))
         return z
 
     def solve(self, b, x=None, nu1=3, nu2=3, omega=0.7, rtol=1e-8, maxit=100, method="cg",
-              precision="f64", stream=None, raise_on_status=True):
+              precision="f64", stream=None, raise_on_status=True, nu_inc=0):
         """A x = b by V-cycle-preconditioned CG (method "cg") or the V-cycle
         iteration (method "cycle") (``hhg_mg_solve``); call setup_coefficient
         first.  precision "f32" runs the V-cycles in FP32 (the outer
@@ -425,7 +426,7 @@ class Multigrid:
         f = self.meshes[-1]
         if x is None:
             x = torch.zeros((3, f.n_nodes), dtype=torch.float64, device=b.device)
-        o = self._opts(nu1, nu2, omega, rtol, maxit, method, precision)
+        o = self._opts(nu1, nu2, omega, rtol, maxit, method, precision, nu_inc)
         info = L.SolveInfo()
         rc = self._lib.hhg_mg_solve(self._mg, ctypes.byref(o), _dev_ptr(b, (3, f.n_nodes), torch.float64),
                                     _dev_ptr(x, (3, f.n_nodes), torch.float64), self._workspace(b.device),
@@ -450,14 +451,15 @@ class Multigrid:
         return ctypes.c_void_p(base + ((-base) % 256))
 
     @staticmethod
-    def _stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit):
+    def _stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit, nu_inc=0):
         return L.StokesOpts(int(nu1), int(nu2), float(omega), float(omega_p), float(h), float(rtol),
-                            int(maxit), 0)
+                            int(maxit), int(nu_inc))
 
     def stokes_solve(self, f, mu, u=None, p=None, g=None, nu1=3, nu2=3, omega=0.7, omega_p=1.0,
-                     h=0.0, rtol=1e-8, maxit=500, stream=None, raise_on_status=True):
+                     h=0.0, rtol=1e-8, maxit=500, stream=None, raise_on_status=True, nu_inc=0):
         """Inexact Uzawa for the generalized Stokes system on the finest
         level (``hhg_mg_stokes_solve``); call setup_coefficient(mu) first.
+        nu_inc: extra velocity smoothing steps per coarser level.
         Returns (u, p, info dict)."""
         import torch
         fm = self.meshes[-1]
@@ -466,7 +468,7 @@ class Multigrid:
             u = torch.zeros((3, N), dtype=torch.float64, device=f.device)
         if p is None:
             p = torch.zeros((N,), dtype=torch.float64, device=f.device)
-        o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit)
+        o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit, nu_inc)
         info = L.SolveInfo()
         gp = _dev_ptr(g, (N,), torch.float64) if g is not None else ctypes.c_void_p(0)
         rc = self._lib.hhg_mg_stokes_solve(self._mg, ctypes.byref(o), _dev_ptr(f, (3, N), torch.float64), gp,
@@ -482,7 +484,7 @@ class Multigrid:
 
     def stokes_picard(self, f, eta0, eta_inf, kappa, r, method="scaled", max_picard=100, nu1=3, nu2=3,
                       omega=0.7, omega_p=1.0, h=0.0, rtol=1e-3, maxit=500, stream=None,
-                      raise_on_status=True, boundary="lsq"):
+                      raise_on_status=True, boundary="lsq", nu_inc=0):
         """Fixed-point iteration for the Carreau fluid (``hhg_mg_stokes_picard``);
         boundary: the strain-rate fit on macro-boundary nodes ("lsq" or
         "average").  Returns (u, p, mu, info dict)."""
@@ -492,7 +494,7 @@ class Multigrid:
         u = torch.empty((3, N), dtype=torch.float64, device=f.device)
         p = torch.empty((N,), dtype=torch.float64, device=f.device)
         mu = torch.empty((N,), dtype=torch.float64, device=f.device)
-        o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit)
+        o = self._stokes_opts(nu1, nu2, omega, omega_p, h, rtol, maxit, nu_inc)
         law = L.Carreau(float(eta0), float(eta_inf), float(kappa), float(r), _strain_fit(boundary))
         m = {"scaled": L.HHG_METHOD_SCALED, "onthefly": L.HHG_METHOD_ONTHEFLY}[method]
         info = L.PicardInfo()

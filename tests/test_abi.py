@@ -124,14 +124,15 @@ def test_null_arguments():
 
 _STRUCTS = {"hhg_mesh_desc": "MeshDesc", "hhg_op_desc": "OpDesc", "hhg_solve_opts": "SolveOpts",
             "hhg_solve_info": "SolveInfo", "hhg_carreau": "Carreau", "hhg_tune_report": "TuneReport",
-            "hhg_train_opts": "TrainOpts", "hhg_mg_opts": "MgOpts"}
+            "hhg_train_opts": "TrainOpts", "hhg_mg_opts": "MgOpts", "hhg_stokes_opts": "StokesOpts",
+            "hhg_picard_info": "PicardInfo", "hhg2d_mesh_desc": "MeshDesc2D"}
 
 
 def declared_structs():
     """Field names, in order, of every typedef struct in the header."""
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     out = {}
-    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(hhg_\w+)\s*;", text, re.S):
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(hhg(?:2d)?_\w+)\s*;", text, re.S):
         fields = []
         for decl in body.split(";"):
             decl = decl.strip()

@@ -85,15 +85,16 @@ def test_vcycle_matches_oracle(name, level):
     k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 0), 16, 1.0)
     H = MG.Hierarchy(V, mg.coarse_level, level, k, EFORM)
     mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda())
-    for seed, (nu1, nu2, omega) in enumerate([(3, 3, 0.7), (1, 2, 0.6)]):
+    for seed, (nu1, nu2, omega, inc) in enumerate([(3, 3, 0.7, 0), (1, 2, 0.6, 0), (3, 3, 0.7, 2)]):
         r, r_d = consistent_random(f, s2n[-1], 30 + seed)
-        z = gather_consistent(mg.vcycle(r_d, nu1=nu1, nu2=nu2, omega=omega).cpu().numpy(),
+        z = gather_consistent(mg.vcycle(r_d, nu1=nu1, nu2=nu2, omega=omega, nu_inc=inc).cpu().numpy(),
                               s2n[-1], f.n_nodes)
-        ref = node_vec(MG.vcycle(H, dof_vec(r, f), nu1=nu1, nu2=nu2, omega=omega), f)
+        ref = node_vec(MG.vcycle(H, dof_vec(r, f), nu1=nu1, nu2=nu2, omega=omega, nu_inc=inc), f)
         u = f.unknown
         assert np.all(z[f.dirichlet] == 0)
         err = rel_err(z[u], ref[u])
-        print(f"  {name} level {level} V({nu1},{nu2}) omega {omega}: rel err {err:.2e}", flush=True)
+        print(f"  {name} level {level} V({nu1},{nu2}) omega {omega} +{inc} per coarser level: "
+              f"rel err {err:.2e}", flush=True)
         assert err <= 1e-10
 
 
@@ -135,6 +136,8 @@ def test_invalid_arguments_rejected():
         mg.vcycle(r, nu1=0, nu2=0)
     with pytest.raises(HHGError):
         mg.vcycle(r, omega=2.5)
+    with pytest.raises(HHGError):
+        mg.vcycle(r, nu_inc=9)
     import ctypes
     from paper_1908_08666_amd import _lib as L
     o = L.MgOpts(3, 3, 0.7, 1e-8, 10, L.HHG_MG_CG, 7)      # unknown cycle precision

@@ -118,6 +118,39 @@ def test_uzawa_matches_oracle():
     assert rel_err(ug, z[:dof.size]) <= 1e-6 and rel_err(pg, z[dof.size:]) <= 1e-5
 
 
+def test_uzawa_with_the_papers_cycle_settings():
+    """The paper's settings of Sec. 5.2.1: variable V(3,3) cycles (two more
+    smoothing steps per coarser level) and pressure relaxation 0.3.  Five
+    steps agree with the oracle's, and the solve converges to 1e-8."""
+    L = 4
+    mg, orc, s2n = _setup(L)
+    mu = 0.5 + W.exp_fourier_coefficient(orc.xyz, W.rng_for(6, 0), 8, 0.5)
+    f = _shear_force(orc)
+    mut = torch.from_numpy(scatter(mu, s2n)).cuda()
+    ft = torch.from_numpy(scatter(f, s2n)).cuda()
+    mg.setup_coefficient(mut)
+    u, p, info = mg.stokes_solve(ft, mut, rtol=0.0, maxit=5, omega_p=0.3, nu_inc=2,
+                                 raise_on_status=False)
+    torch.cuda.synchronize()
+    H = MG.Hierarchy(W.kuhn6(), 2, L, mu, dict(mu1=1.0))
+    dof = O.unknown_dofs(orc)
+    uo, po, it, hist = ST.inexact_uzawa(H, orc, mu, f.ravel()[dof], rtol=0.0, maxit=5, omega_p=0.3,
+                                        nu_inc=2)
+    ug = _vel_gather(u.cpu().numpy(), s2n, orc.n_nodes).ravel()[dof]
+    pg = _pressure_gather(p.cpu().numpy(), s2n, orc.n_nodes)
+    print(f"  5 Uzawa steps, variable cycle, omega_p 0.3: u {rel_err(ug, uo):.2e}, "
+          f"p {rel_err(pg, po):.2e}", flush=True)
+    assert rel_err(ug, uo) <= 1e-9 and rel_err(pg, po) <= 1e-9
+    assert abs(info["rel_residual"] - hist[-1]) <= 1e-9 * hist[-1]
+    steps = {}
+    for name, kw in (("fixed, omega_p 1", dict()), ("variable, omega_p 0.3", dict(omega_p=0.3, nu_inc=2)),
+                     ("variable, omega_p 1", dict(nu_inc=2))):
+        _, _, inf = mg.stokes_solve(ft, mut, rtol=1e-8, maxit=800, **kw)
+        torch.cuda.synchronize()
+        steps[name] = inf["iterations"]
+    print(f"  Uzawa steps to 1e-8: {steps}", flush=True)
+
+
 @pytest.mark.parametrize("method", ["scaled", "onthefly"])
 def test_picard_matches_oracle(method):
     """Carreau fixed-point iteration (Alg. fixedpoint_mg) on the 6-macro cube

@@ -90,6 +90,35 @@ def test_vcycle_contracts_independently_of_the_level(hierarchies):
     assert rates[4] < rates[3] + 0.15, rates
 
 
+def test_variable_vcycle(hierarchies):
+    """The variable V-cycle (Sec. 5.2.1: more smoothing on coarser levels)
+    stays symmetric, adds smoothing only below the finest level (on a
+    two-level hierarchy, whose coarse level is solved exactly, it is the
+    fixed cycle), and contracts at least as fast as the fixed cycle with the
+    same finest-level smoothing."""
+    H = hierarchies[4]
+    A = H.A[-1]
+    n = A.shape[0]
+    r1 = W.uniform_vector(n, W.rng_for(9, 3))
+    r2 = W.uniform_vector(n, W.rng_for(9, 4))
+    a = MG.vcycle(H, r1, nu_inc=2) @ r2
+    b = r1 @ MG.vcycle(H, r2, nu_inc=2)
+    assert abs(a - b) <= 1e-10 * abs(a)
+    assert np.array_equal(MG.vcycle(H, r1, nu_inc=0), MG.vcycle(H, r1))
+    assert np.abs(MG.vcycle(H, r1, nu_inc=2) - MG.vcycle(H, r1)).max() > 1e-8 * np.abs(MG.vcycle(H, r1)).max()
+    two = MG.Hierarchy(W.kuhn6(), 3, 4, H.k[-1], EFORM)
+    assert np.array_equal(MG.vcycle(two, r1, nu_inc=2), MG.vcycle(two, r1))
+    rates = {}
+    for inc in (0, 2):
+        x = np.zeros(n)
+        res = [np.linalg.norm(r1)]
+        for _ in range(6):
+            x = x + MG.vcycle(H, r1 - A @ x, nu_inc=inc)
+            res.append(np.linalg.norm(r1 - A @ x))
+        rates[inc] = (res[-1] / res[2]) ** 0.25
+    assert rates[2] <= rates[0], rates
+
+
 def test_mg_pcg_matches_direct_solve(hierarchies):
     for L, H in hierarchies.items():
         A = H.A[-1]
