@@ -459,6 +459,24 @@ __global__ __launch_bounds__(256) void k_finish(const int64_t *__restrict__ ptr,
   }
 }
 
+// Boundary part of a damped block-Jacobi step: xo = x + omega P r on the
+// macro-boundary slots (r complete there after the copy-group sum).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bjacobi(const int64_t *__restrict__ bnd, int64_t nb,
+                                                 const T *__restrict__ P, const T *__restrict__ r,
+                                                 const T *__restrict__ x, T *__restrict__ xo,
+                                                 T omega, int64_t nn) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nb) return;
+  const int64_t s = bnd[q];
+  const T r0 = r[s], r1 = r[nn + s], r2 = r[2 * nn + s];
+  const T Pxx = P[s], Pyy = P[nn + s], Pzz = P[2 * nn + s];
+  const T Pxy = P[3 * nn + s], Pxz = P[4 * nn + s], Pyz = P[5 * nn + s];
+  xo[s] = x[s] + omega * (Pxx * r0 + Pxy * r1 + Pxz * r2);
+  xo[nn + s] = x[nn + s] + omega * (Pxy * r0 + Pyy * r1 + Pyz * r2);
+  xo[2 * nn + s] = x[2 * nn + s] + omega * (Pxz * r0 + Pyz * r1 + Pzz * r2);
+}
+
 // ------------------------------------------------------------ launchers
 namespace {
 
@@ -566,6 +584,41 @@ int apply_dot_t(hhg_ctx *h, int method, const T *x, const T *k, T *y, double *pa
   return rc;
 }
 
+// One damped block-Jacobi step xo = x + omega P (f - A x) (xo must not alias
+// x): the interior kernel applies the step to the macro-interior rows in its
+// epilogue, so their residual never goes to memory; the boundary rows and the
+// copy sums write the residual of the macro-boundary rows to r as in a
+// residual apply (same streams as apply_t), and k_bjacobi completes the step
+// there.
+template <typename T>
+int smooth_t(hhg_ctx *h, int method, const T *f, const T *x, const T *k, const T *P, T omega,
+             T *r, T *xo, hipStream_t st) {
+  auto interior = [&](hipStream_t s) {
+    return method == METHOD_SCALED
+               ? launch_interior_smooth<T, METHOD_SCALED>(h, x, k, f, P, omega, xo, s)
+               : launch_interior_smooth<T, METHOD_ONTHEFLY>(h, x, k, f, P, omega, xo, s);
+  };
+  int rc;
+  if (h->serial_apply) {
+    if ((rc = interior(st))) return rc;
+    if ((rc = launch_boundary<T, true>(h, method, x, k, f, r, st))) return rc;
+  } else {
+    HHG_HIP(hipEventRecord(h->ev_fork, st));
+    HHG_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    rc = launch_boundary<T, true>(h, method, x, k, f, r, h->side);
+    if (!rc) rc = interior(st);
+    HHG_HIP(hipEventRecord(h->ev_join, h->side));
+    HHG_HIP(hipStreamWaitEvent(st, h->ev_join, 0));
+    if (rc) return rc;
+  }
+  if (h->n_bnd > 0) {
+    hipLaunchKernelGGL(k_bjacobi<T>, dim3((unsigned)((h->n_bnd + 255) / 256)), dim3(256), 0, st,
+                       h->d_bnd, h->n_bnd, P, r, x, xo, omega, h->n_nodes);
+    HHG_HIP(hipGetLastError());
+  }
+  return HHG_OK;
+}
+
 bool overlaps(const void *a, const void *b, size_t bytes) {
   const char *pa = (const char *)a, *pb = (const char *)b;
   return pa < pb + bytes && pb < pa + bytes;
@@ -619,6 +672,18 @@ int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *
                            (double *)y, st);
   return apply_t<float>(h, method, (const float *)f, (const float *)x, (const float *)k,
                         (float *)y, st);
+}
+
+// One damped block-Jacobi smoothing step for the multigrid (see smooth_t).
+int smooth_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
+                    const void *P, double omega, void *r, void *xo, hipStream_t st) {
+  int rc = ensure_device(h);
+  if (rc) return rc;
+  if (prec == HHG_F64)
+    return smooth_t<double>(h, method, (const double *)f, (const double *)x, (const double *)k,
+                            (const double *)P, omega, (double *)r, (double *)xo, st);
+  return smooth_t<float>(h, method, (const float *)f, (const float *)x, (const float *)k,
+                         (const float *)P, (float)omega, (float *)r, (float *)xo, st);
 }
 
 }  // namespace hhg

@@ -27,6 +27,7 @@ struct hhg_ctx {
   std::vector<int32_t> bblk;                 // macro of each boundary-row block
   std::vector<hhg::FaceTile> ftile;          // tiles of face-interior rows (non-Dirichlet faces)
   std::vector<int64_t> dslot;                // Dirichlet slots (rows written as zero)
+  std::vector<int64_t> bnd;                  // every macro-boundary slot (flag bit 2)
   std::vector<int64_t> grp_ptr, grp_slot;    // non-Dirichlet copy groups
   std::vector<int64_t> agrp_ptr, agrp_slot;  // all copy groups
   int wl_max = 0;                            // LDS window entries per plane
@@ -50,6 +51,8 @@ struct hhg_ctx {
   int32_t *d_bblk = nullptr;
   hhg::FaceTile *d_ftile = nullptr;
   int64_t *d_dslot = nullptr;
+  int64_t *d_bnd = nullptr;
+  int64_t n_bnd = 0;
   int64_t *d_grp_ptr = nullptr;              // interface copy groups (>= 2 copies)
   int64_t *d_grp_slot = nullptr;
   int64_t n_grp = 0;

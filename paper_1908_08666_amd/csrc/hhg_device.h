@@ -68,5 +68,8 @@ template <typename T, int METHOD, bool RESID>
 int launch_interior_v(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipStream_t st);
 template <typename T, int METHOD>
 int launch_interior_dot(hhg_ctx *h, const T *x, const T *k, T *y, double *part, hipStream_t st);
+template <typename T, int METHOD>
+int launch_interior_smooth(hhg_ctx *h, const T *x, const T *k, const T *f, const T *P, T omega,
+                           T *xo, hipStream_t st);
 
 }  // namespace hhg

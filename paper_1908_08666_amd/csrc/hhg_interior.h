@@ -112,8 +112,10 @@ __device__ __forceinline__ void interior_item(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part, int item) {
-  static_assert(OUT >= 0 && OUT <= 2, "output: 0 apply, 1 residual, 2 apply and (x, y) partial sum");
+    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part, int item,
+    const T *__restrict__ P, T omega, T *__restrict__ xo) {
+  static_assert(OUT >= 0 && OUT <= 3,
+                "output: 0 apply, 1 residual, 2 apply and (x, y) partial sum, 3 smoothing step");
   Pair<T> *bufA = reinterpret_cast<Pair<T> *>(smem_raw);   // 3 planes of (x0, x1)
   Pair<T> *bufB = bufA + 3 * wl;                             // 3 planes of (x2, k)
   const MacroInfo mi = minfo[w.macro];
@@ -255,7 +257,19 @@ __device__ __forceinline__ void interior_item(
     for (int u = 0; u < NSUB; ++u)
       if (act[u]) {
         const int64_t g = gk + ps_[u];
-        if constexpr (OUT == 1) {
+        if constexpr (OUT == 3) {
+          // damped block-Jacobi step x_out = x + omega P (f - A x) with the
+          // node's 3x3 block P (xx yy zz xy xz yz); x of the node is still in
+          // the LDS slot of plane kk
+          const int o0 = (kk % 3) * wl + ps_[u] - ws;
+          const Pair<T> xa = bufA[o0], xb = bufB[o0];
+          const T r0 = f[g] - yv[u][0], r1 = f[g + nn] - yv[u][1], r2 = f[g + 2 * nn] - yv[u][2];
+          const T Pxx = P[g], Pyy = P[g + nn], Pzz = P[g + 2 * nn];
+          const T Pxy = P[g + 3 * nn], Pxz = P[g + 4 * nn], Pyz = P[g + 5 * nn];
+          xo[g] = xa.a + omega * (Pxx * r0 + Pxy * r1 + Pxz * r2);
+          xo[g + nn] = xa.b + omega * (Pxy * r0 + Pyy * r1 + Pyz * r2);
+          xo[g + 2 * nn] = xb.a + omega * (Pxz * r0 + Pyz * r1 + Pzz * r2);
+        } else if constexpr (OUT == 1) {
           y[g] = f[g] - yv[u][0];
           y[g + nn] = f[g + nn] - yv[u][1];
           y[g + 2 * nn] = f[g + 2 * nn] - yv[u][2];
@@ -290,7 +304,8 @@ __global__ __launch_bounds__(TPB) void k_interior(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part) {
+    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part, const T *__restrict__ P,
+    T omega, T *__restrict__ xo) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const WorkItem w = work[blockIdx.x];
   if (w.macro < 0) {                        // padding item of the XCD-aware order
@@ -302,7 +317,7 @@ __global__ __launch_bounds__(TPB) void k_interior(
     return;
   }
   interior_item<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc, f,
-                                                         y, nn, wl, part, blockIdx.x);
+                                                         y, nn, wl, part, blockIdx.x, P, omega, xo);
 }
 
 // Persistent form: a grid of resident workgroups walks the work list with a
@@ -315,13 +330,14 @@ __global__ __launch_bounds__(TPB) void k_interior_persist(
     const MacroInfo *__restrict__ minfo, const StencilConst<T> *__restrict__ scs,
     const ElemConst<T> *__restrict__ ecs, const WorkItem *__restrict__ work, int n_work,
     const T *__restrict__ x, const T *__restrict__ kc, const T *__restrict__ f,
-    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part) {
+    T *__restrict__ y, int64_t nn, int wl, double *__restrict__ part, const T *__restrict__ P,
+    T omega, T *__restrict__ xo) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   for (int q = blockIdx.x; q < n_work; q += gridDim.x) {
     const WorkItem w = work[q];
     if (w.macro >= 0)                       // block-uniform
       interior_item<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>(w, smem_raw, minfo, scs, ecs, x, kc,
-                                                             f, y, nn, wl, part, q);
+                                                             f, y, nn, wl, part, q, P, omega, xo);
     else if (OUT == 2 && threadIdx.x == 0) {
       part[3 * q] = 0.0;
       part[3 * q + 1] = 0.0;
@@ -334,7 +350,7 @@ __global__ __launch_bounds__(TPB) void k_interior_persist(
 
 template <typename T, int METHOD, int OUT, bool CORR, bool A0, int NW, int TPB, int NSUB>
 int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, double *part,
-                       hipStream_t st) {
+                       hipStream_t st, const T *P, T omega, T *xo) {
   const int wl = h->wl_max;
   const size_t lds = 6 * (size_t)wl * sizeof(Pair<T>);
   ProfScope prof(h, METHOD == METHOD_SCALED ? HHG_K_INTERIOR_SCALED : HHG_K_INTERIOR_ONTHEFLY, st);
@@ -344,13 +360,13 @@ int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, dou
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(std::min(h->persist_blocks, h->n_work)), dim3(TPB), lds, st,
                        h->d_minfo, sc_ptr<T>(h), ec_ptr<T>(h), h->d_work, h->n_work, x, k, f, y,
-                       h->n_nodes, wl, part);
+                       h->n_nodes, wl, part, P, omega, xo);
   } else {
     auto kern = k_interior<T, METHOD, OUT, CORR, A0, NW, TPB, NSUB>;
     if (lds > 65536) HHG_HIP(hipFuncSetAttribute((const void *)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(h->n_work), dim3(TPB), lds, st, h->d_minfo, sc_ptr<T>(h),
-                       ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl, part);
+                       ec_ptr<T>(h), h->d_work, x, k, f, y, h->n_nodes, wl, part, P, omega, xo);
   }
   HHG_HIP(hipGetLastError());
   return HHG_OK;
@@ -360,23 +376,25 @@ int launch_interior_nw(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, dou
 // to 2 (levels <= 7) or up to 6 (level 8).
 template <typename T, int METHOD, int OUT, bool CORR, bool A0>
 int launch_interior(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, double *part,
-                    hipStream_t st) {
+                    hipStream_t st, const T *P, T omega, T *xo) {
   if (h->n_work == 0) return HHG_OK;
   const int nw = (h->wl_max + 255) / 256;
-  if (nw <= 2) return launch_interior_nw<T, METHOD, OUT, CORR, A0, 2, 256, 1>(h, x, k, f, y, part, st);
-  if (nw <= 6) return launch_interior_nw<T, METHOD, OUT, CORR, A0, 6, 256, 1>(h, x, k, f, y, part, st);
+  if (nw <= 2)
+    return launch_interior_nw<T, METHOD, OUT, CORR, A0, 2, 256, 1>(h, x, k, f, y, part, st, P, omega, xo);
+  if (nw <= 6)
+    return launch_interior_nw<T, METHOD, OUT, CORR, A0, 6, 256, 1>(h, x, k, f, y, part, st, P, omega, xo);
   return fail(HHG_EINVAL, "interior window larger than supported");
 }
 
 template <typename T, int METHOD, int OUT>
 int launch_interior_o(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, double *part,
-                      hipStream_t st) {
+                      hipStream_t st, const T *P = nullptr, T omega = T(0), T *xo = nullptr) {
   const bool corr = METHOD == METHOD_SCALED && h->op.corr == HHG_CORR_PHYSICAL;
   const bool a0 = h->op.mu0 != 0.0 || h->op.lam0 != 0.0;
-  if (corr && a0) return launch_interior<T, METHOD, OUT, true, true>(h, x, k, f, y, part, st);
-  if (corr) return launch_interior<T, METHOD, OUT, true, false>(h, x, k, f, y, part, st);
-  if (a0) return launch_interior<T, METHOD, OUT, false, true>(h, x, k, f, y, part, st);
-  return launch_interior<T, METHOD, OUT, false, false>(h, x, k, f, y, part, st);
+  if (corr && a0) return launch_interior<T, METHOD, OUT, true, true>(h, x, k, f, y, part, st, P, omega, xo);
+  if (corr) return launch_interior<T, METHOD, OUT, true, false>(h, x, k, f, y, part, st, P, omega, xo);
+  if (a0) return launch_interior<T, METHOD, OUT, false, true>(h, x, k, f, y, part, st, P, omega, xo);
+  return launch_interior<T, METHOD, OUT, false, false>(h, x, k, f, y, part, st, P, omega, xo);
 }
 
 template <typename T, int METHOD, bool RESID>
@@ -390,6 +408,15 @@ int launch_interior_v(hhg_ctx *h, const T *x, const T *k, const T *f, T *y, hipS
 template <typename T, int METHOD>
 int launch_interior_dot(hhg_ctx *h, const T *x, const T *k, T *y, double *part, hipStream_t st) {
   return launch_interior_o<T, METHOD, 2>(h, x, k, nullptr, y, part, st);
+}
+
+// One damped block-Jacobi step on the macro-interior rows:
+// xo = x + omega P (f - A x), P the 3x3 blocks [6][n_nodes] (xx yy zz xy xz
+// yz); xo must not alias x (other rows read x while it is written).
+template <typename T, int METHOD>
+int launch_interior_smooth(hhg_ctx *h, const T *x, const T *k, const T *f, const T *P, T omega,
+                           T *xo, hipStream_t st) {
+  return launch_interior_o<T, METHOD, 3>(h, x, k, f, nullptr, nullptr, st, P, omega, xo);
 }
 
 

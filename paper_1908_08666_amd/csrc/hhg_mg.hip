@@ -32,6 +32,8 @@ namespace hhg {
 
 int apply_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
                    void *y, hipStream_t st);
+int smooth_internal(hhg_ctx *h, int prec, int method, const void *f, const void *x, const void *k,
+                    const void *P, double omega, void *r, void *xo, hipStream_t st);
 
 namespace {
 
@@ -304,8 +306,8 @@ __global__ void k_xpby(double *__restrict__ p, const double *__restrict__ z, dou
 
 // ----------------------------------------------------------- workspace
 struct MgWork {
-  std::vector<double *> k, P, b, x, r;   // per level
-  std::vector<float *> k32, P32, b32, x32, r32;   // per level, for FP32 cycles
+  std::vector<double *> k, P, b, x, r, xs;   // per level (xs: second iterate of the smoother)
+  std::vector<float *> k32, P32, b32, x32, r32, xs32;   // per level, for FP32 cycles
   double *Ainv = nullptr;                // (3 n_cu)^2, inverse of the coarsest operator
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;   // CG vectors (finest)
   double *part = nullptr;                // MG_RED partial sums
@@ -315,17 +317,17 @@ struct MgWork {
 template <typename T>
 struct LevelArrays {
   const T *k, *P;
-  T *b, *x, *r;
+  T *b, *x, *r, *xs;
 };
 template <typename T>
 LevelArrays<T> level_arrays(const MgWork &W, int q);
 template <>
 LevelArrays<double> level_arrays<double>(const MgWork &W, int q) {
-  return {W.k[q], W.P[q], W.b[q], W.x[q], W.r[q]};
+  return {W.k[q], W.P[q], W.b[q], W.x[q], W.r[q], W.xs[q]};
 }
 template <>
 LevelArrays<float> level_arrays<float>(const MgWork &W, int q) {
-  return {W.k32[q], W.P32[q], W.b32[q], W.x32[q], W.r32[q]};
+  return {W.k32[q], W.P32[q], W.b32[q], W.x32[q], W.r32[q], W.xs32[q]};
 }
 template <typename T>
 constexpr int prec_of() {
@@ -354,11 +356,13 @@ size_t layout(const hhg_mg_s *mg, char *base, MgWork *w) {
   W.b.assign(L, nullptr);
   W.x.assign(L, nullptr);
   W.r.assign(L, nullptr);
+  W.xs.assign(L, nullptr);
   W.k32.assign(L, nullptr);
   W.P32.assign(L, nullptr);
   W.b32.assign(L, nullptr);
   W.x32.assign(L, nullptr);
   W.r32.assign(L, nullptr);
+  W.xs32.assign(L, nullptr);
   for (int q = 0; q < L; ++q) {
     const size_t N = (size_t)mg->lev[q]->n_nodes;
     W.k[q] = take(8 * N);
@@ -366,11 +370,13 @@ size_t layout(const hhg_mg_s *mg, char *base, MgWork *w) {
     W.b[q] = take(24 * N);
     W.x[q] = take(24 * N);
     W.r[q] = take(24 * N);
+    W.xs[q] = take(24 * N);
     W.k32[q] = take32(4 * N);
     W.P32[q] = take32(24 * N);
     W.b32[q] = take32(12 * N);
     W.x32[q] = take32(12 * N);
     W.r32[q] = take32(12 * N);
+    W.xs32[q] = take32(12 * N);
   }
   const size_t n3 = 3 * (size_t)mg->n_cu;
   W.Ainv = take(8 * n3 * n3);
@@ -481,24 +487,29 @@ int vcycle(hhg_mg_s *mg, const MgWork &W, const hhg_mg_opts &o, int q, const T *
   const LevelArrays<T> A = level_arrays<T>(W, q), C = level_arrays<T>(W, q - 1);
   T *r = A.r;
   const T omega = (T)o.omega;
+  // Every smoothing step after the first writes the other of two iterates
+  // (x and the level's spare xs); start in the one that makes the last step
+  // land in x.
+  const int steps = (nu1 > 0 ? nu1 - 1 : 0) + nu2;
+  T *cur = (steps % 2 == 0) ? x : A.xs, *oth = (steps % 2 == 0) ? A.xs : x;
   auto smooth = [&](bool first) -> int {
     if (first) {
-      hipLaunchKernelGGL((k_jacobi<true, T>), grid1(N), dim3(256), 0, st, A.P, b, x, omega, N);
-    } else {
-      const int rc2 = apply_internal(h, prec_of<T>(), mg->method, b, x, A.k, r, st);
-      if (rc2) return rc2;
-      hipLaunchKernelGGL((k_jacobi<false, T>), grid1(N), dim3(256), 0, st, A.P, r, x, omega, N);
+      hipLaunchKernelGGL((k_jacobi<true, T>), grid1(N), dim3(256), 0, st, A.P, b, cur, omega, N);
+      HHG_HIP(hipGetLastError());
+      return HHG_OK;
     }
-    HHG_HIP(hipGetLastError());
-    return HHG_OK;
+    const int rc2 = smooth_internal(h, prec_of<T>(), mg->method, b, cur, A.k, A.P, (double)omega, r,
+                                    oth, st);
+    std::swap(cur, oth);
+    return rc2;
   };
   for (int s = 0; s < nu1; ++s)
     if ((rc = smooth(s == 0))) return rc;
-  if (nu1 == 0) hipLaunchKernelGGL(k_fill0<T>, grid1(3 * N), dim3(256), 0, st, x, 3 * N);
-  if ((rc = apply_internal(h, prec_of<T>(), mg->method, b, x, A.k, r, st))) return rc;
+  if (nu1 == 0) hipLaunchKernelGGL(k_fill0<T>, grid1(3 * N), dim3(256), 0, st, cur, 3 * N);
+  if ((rc = apply_internal(h, prec_of<T>(), mg->method, b, cur, A.k, r, st))) return rc;
   if ((rc = restrict_<T>(mg, q, r, C.b, st))) return rc;
   if ((rc = vcycle<T>(mg, W, o, q - 1, C.b, C.x, st))) return rc;
-  if ((rc = prolong<T>(mg, q, C.x, x, true, st))) return rc;
+  if ((rc = prolong<T>(mg, q, C.x, cur, true, st))) return rc;
   for (int s = 0; s < nu2; ++s)
     if ((rc = smooth(false))) return rc;
   return HHG_OK;

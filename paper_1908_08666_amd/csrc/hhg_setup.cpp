@@ -386,6 +386,7 @@ void free_ctx(hhg_ctx *h) {
   dfree(h->d_bblk);
   dfree(h->d_ftile);
   dfree(h->d_dslot);
+  dfree(h->d_bnd);
   dfree(h->d_grp_ptr);
   dfree(h->d_grp_slot);
   dfree(h->d_flags);
@@ -677,6 +678,12 @@ int setup_impl(const hhg_mesh_desc *mesh, const hhg_op_desc *op, hhg_ctx *h) {
   h->bblk = std::move(bblk);
   h->ftile = std::move(ftile);
   h->dslot = std::move(dslot);
+  // every macro-boundary slot: the rows that the boundary-row kernel and the
+  // copy-group sum complete, for the boundary part of a smoothing step
+  h->bnd.clear();
+  for (int64_t s = 0; s < h->n_nodes; ++s)
+    if (h->flags[(size_t)s] & 4) h->bnd.push_back(s);
+  h->n_bnd = (int64_t)h->bnd.size();
   h->grp_ptr = std::move(gptr);
   h->grp_slot = std::move(gslot);
   return HHG_OK;
@@ -805,6 +812,7 @@ int ensure_device(hhg_ctx *h) {
   if ((rc = upload(&h->d_bblk, h->bblk.data(), h->bblk.size()))) return rc;
   if ((rc = upload(&h->d_ftile, h->ftile.data(), h->ftile.size()))) return rc;
   if ((rc = upload(&h->d_dslot, h->dslot.data(), h->dslot.size()))) return rc;
+  if ((rc = upload(&h->d_bnd, h->bnd.data(), h->bnd.size()))) return rc;
   if ((rc = upload(&h->d_grp_ptr, h->grp_ptr.data(), h->grp_ptr.size()))) return rc;
   if ((rc = upload(&h->d_grp_slot, h->grp_slot.data(), h->grp_slot.size()))) return rc;
   if ((rc = upload(&h->d_flags, h->flags.data(), h->flags.size()))) return rc;
