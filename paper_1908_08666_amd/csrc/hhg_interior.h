@@ -214,11 +214,24 @@ __device__ __forceinline__ void interior_item(
     const int64_t gk = mi.off + plane_base(n, kk);
     T yv[NSUB][3];
     bool act[NSUB];
+    // smoothing step: b and the node's block are loaded before the stencil,
+    // so that their latency hides behind it (the kernel runs at two waves
+    // per SIMD either way)
+    T sb[NSUB][9];
 #pragma unroll
     for (int u = 0; u < NSUB; ++u) {
       const int p = ps_[u], sp = ss_[u];
       act[u] = col_ok[u] && sp + kk <= n - 1;
       yv[u][0] = yv[u][1] = yv[u][2] = T(0);
+      if constexpr (OUT == 3) {
+        if (act[u]) {
+          const int64_t g = gk + p;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sb[u][c] = f[g + c * nn];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sb[u][3 + c] = P[g + c * nn];
+        }
+      }
       if (act[u]) {
         const int e0 = p - ws;
         const int om = ((kk + 2) % 3) * wl + e0;   // plane kk-1
@@ -263,9 +276,9 @@ __device__ __forceinline__ void interior_item(
           // the LDS slot of plane kk
           const int o0 = (kk % 3) * wl + ps_[u] - ws;
           const Pair<T> xa = bufA[o0], xb = bufB[o0];
-          const T r0 = f[g] - yv[u][0], r1 = f[g + nn] - yv[u][1], r2 = f[g + 2 * nn] - yv[u][2];
-          const T Pxx = P[g], Pyy = P[g + nn], Pzz = P[g + 2 * nn];
-          const T Pxy = P[g + 3 * nn], Pxz = P[g + 4 * nn], Pyz = P[g + 5 * nn];
+          const T r0 = sb[u][0] - yv[u][0], r1 = sb[u][1] - yv[u][1], r2 = sb[u][2] - yv[u][2];
+          const T Pxx = sb[u][3], Pyy = sb[u][4], Pzz = sb[u][5];
+          const T Pxy = sb[u][6], Pxz = sb[u][7], Pyz = sb[u][8];
           xo[g] = xa.a + omega * (Pxx * r0 + Pxy * r1 + Pxz * r2);
           xo[g + nn] = xa.b + omega * (Pxy * r0 + Pyy * r1 + Pyz * r2);
           xo[g + 2 * nn] = xb.a + omega * (Pxz * r0 + Pyz * r1 + Pzz * r2);
