@@ -85,7 +85,10 @@ def test_vcycle_matches_oracle(name, level):
     k = W.exp_fourier_coefficient(f.xyz, W.rng_for(2, 0), 16, 1.0)
     H = MG.Hierarchy(V, mg.coarse_level, level, k, EFORM)
     mg.setup_coefficient(torch.from_numpy(scatter(k, s2n[-1])).cuda())
-    for seed, (nu1, nu2, omega, inc) in enumerate([(3, 3, 0.7, 0), (1, 2, 0.6, 0), (3, 3, 0.7, 2)]):
+    # smoothing-step counts of both parities (the fused steps alternate
+    # between two iterates), no pre- or no post-smoothing, variable cycles
+    for seed, (nu1, nu2, omega, inc) in enumerate([(3, 3, 0.7, 0), (1, 2, 0.6, 0), (3, 3, 0.7, 2),
+                                                   (0, 2, 0.7, 0), (2, 0, 0.7, 1)]):
         r, r_d = consistent_random(f, s2n[-1], 30 + seed)
         z = gather_consistent(mg.vcycle(r_d, nu1=nu1, nu2=nu2, omega=omega, nu_inc=inc).cpu().numpy(),
                               s2n[-1], f.n_nodes)
