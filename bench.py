@@ -457,8 +457,8 @@ def main():
         args.extra = args.solve = args.batch = args.learned = args.carreau = args.elastostatics = True
         args.carreau_profile = args.twod = True
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path "
-              f"is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); sharding the macros "
+              f"across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

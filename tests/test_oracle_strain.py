@@ -79,7 +79,7 @@ def test_carreau_law():
 def test_carreau_values_by_hand():
     """Eq. carreau at points where 1 + kappa |eps|^2 is a perfect power, so the
     value follows by hand: 16^(-1/4) = 1/2 and 81^(-1/4) = 1/3 with the
-    constants of this build (eta0 1, eta_inf 1e-3, kappa 1, r -1/4); and the
+    library's default constants (eta0 1, eta_inf 1e-3, kappa 1, r -1/4); and the
     paper's dimensionless blood constants (Sec. 5.2.2: eta0 140.764, eta_inf
     1, kappa 212.2, r -0.325) at 1 + kappa |eps|^2 = 2^(40/13), where the
     power is 2^(-1) exactly."""
